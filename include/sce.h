@@ -1,0 +1,185 @@
+/*
+ * sce.h -- C ABI of the MI355X (gfx950) spectral canonical electrostatic
+ * library: the per-step particle x mode sums of the gridless spectral
+ * macroparticle method of Webb, "A Spectral Canonical Electrostatic
+ * Algorithm" (arXiv:1508.07344), inside its symplectic leapfrog step.
+ *
+ * Model (periodic box [0, L)^3, V = L^3, permittivity eps0):
+ *   modes      n in Z^3 with max_i |n_i| <= n_max and n != 0; k_n = 2 pi n / L.
+ *              Mode spacing 2 pi / L keeps the box periodic (Section 8).
+ *              The n = 0 mode is left out: a uniform neutralising background.
+ *   half space H = { n_x > 0 } u { n_x = 0, n_y > 0 } u { n_x = n_y = 0, n_z > 0 }.
+ *              Every mode pairs with its negative so the potential is real
+ *              (Section 4); only H is stored, |H| = ((2 n_max + 1)^3 - 1) / 2.
+ *              Canonical order: n_x = 0..n_max, then n_y = -n_max..n_max, then
+ *              n_z = -n_max..n_max, skipping modes outside H.
+ *   shape S(k) Fourier transform of the particle shape with S(0) = 1
+ *              (Section 3): point 1, Gaussian exp(-|k|^2 a^2 / 2), or
+ *              tent prod_d sinc^2(k_d a / 2).
+ *   deposit    rho_n = S(k_n) sum_j q_j exp(-i k_n . x_j)
+ *              (right-hand side of the discrete Poisson equation, Section 4).
+ *   solve      phi_n = rho_n / (eps0 |k_n|^2): the delta field shape makes the
+ *              k-squared matrix diagonal (Section 3, Section 4).
+ *   force      F_j = -dW/dx_j = 2 q_j sum_{n in H} k_n Im(psi_n exp(i k_n . x_j)),
+ *              psi_n = S(k_n) phi_n / V (the kick of the discrete
+ *              Euler-Lagrange equations, Section 4).
+ *   energy     W = (1 / (eps0 V)) sum_{n in H} |rho_n|^2 / |k_n|^2;
+ *              kinetic K = 1/2 sum m |v|^2; total E = K + W.
+ *   step       kick-drift-kick (default): v += (h/2) F/m, x = wrap(x + h v),
+ *              F = F(x), v += (h/2) F/m, the end force reused by the next step;
+ *              or drift-kick-drift, the velocity form the paper derives
+ *              (Section 4): x = wrap(x + (h/2) v), F = F(x), v += h F/m,
+ *              x = wrap(x + (h/2) v).  wrap(x) = x - L floor(x / L) in [0, L).
+ *
+ * Conventions for every entry point:
+ *   - Returns sce_status: SCE_OK (0) or a negative error code.  No exception
+ *     or signal crosses the ABI.  After an error, sce_last_error() holds a
+ *     message.  SCE_EDEVICE (a HIP runtime error) leaves the context unusable.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - All device work is enqueued on the context's stream (its own, or the
+ *     one given to sce_set_options).  Calls that return data to host memory
+ *     synchronise that stream before returning.
+ *   - Arrays of particle vectors are structure-of-arrays: [3][N] doubles
+ *     (all x components, then all y, then all z).
+ *   - on_device = 0: pointers are host memory, borrowed only for the call.
+ *     on_device = 1: pointers are device memory on the context's device
+ *     (for example a torch tensor's data_ptr()); they are borrowed until the
+ *     call's work on the stream has finished (sce_sync).
+ *   - The library owns every buffer it allocates and never frees caller memory.
+ */
+#ifndef SCE_H
+#define SCE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCE_OK = 0,
+    SCE_EINVAL = -1,     /* bad argument (non-finite or out-of-range value, NULL pointer) */
+    SCE_ENOMEM = -2,     /* device or host allocation failed */
+    SCE_EDEVICE = -3,    /* HIP runtime error; the context is unusable afterwards */
+    SCE_ESTATE = -4,     /* call made in the wrong state (e.g. no particles set) */
+    SCE_ENOTSUP = -5,    /* unsupported option combination */
+    SCE_EUNSTABLE = -6   /* non-finite energy found by sce_diagnostics */
+} sce_status;
+
+typedef enum { SCE_SHAPE_DELTA = 0, SCE_SHAPE_GAUSSIAN = 1, SCE_SHAPE_TENT = 2 } sce_shape_kind;
+
+/* Arithmetic of the two particle x mode sums.  Positions, velocities, the
+ * drift, the phase anchors, the cross-tile rho sums and the energy and
+ * momentum reductions are FP64 in every mode. */
+typedef enum {
+    SCE_PREC_FP64 = 0,       /* FP64 phases, products and sums */
+    SCE_PREC_FP32 = 1,       /* FP32 phase tables, FP32 products, FP32 sums within a particle tile */
+    SCE_PREC_SPLIT_F16 = 2   /* FP16 hi+lo split products on the matrix cores, FP32 accumulation */
+} sce_precision;
+
+typedef enum { SCE_SCHEME_KDK = 0, SCE_SCHEME_DKD = 1 } sce_scheme;
+
+typedef struct sce_ctx_s *sce_ctx;
+
+/* Diagnostics at the current state (Section 6 reports energy and its kinetic,
+ * capacitive and field parts, and the total momentum). */
+typedef struct {
+    int64_t step;              /* steps taken since the particles were set */
+    double time;               /* sum of dt over those steps */
+    double kinetic;            /* K = 1/2 sum m |v|^2 */
+    double field;              /* W = (1/(eps0 V)) sum_H |rho|^2/|k|^2 at the current positions */
+    double field_self;         /* (sum q^2/(eps0 V)) sum_H S^2/|k|^2: constant self-energy within W */
+    double interaction;        /* sum_j q_j Phi_j, Phi_j = 2 sum_H Re(psi e^{i k.x_j}); equals 2 W */
+    double total;              /* K + W */
+    double momentum[3];        /* sum m v */
+    double momentum_abs_sum;   /* sum m |v| (scale for relative momentum error) */
+    double rho_abs_max;        /* max_H |rho_n| */
+} sce_diag;
+
+/* Create a context for a periodic box of side L with modes max|n_i| <= n_max.
+ * shape_kind: sce_shape_kind; shape_width: Gaussian width a or tent half-width
+ * (ignored for SCE_SHAPE_DELTA).  Builds the mode and Green-function tables on
+ * the current HIP device.  Defaults: eps0 = 1, SCE_PREC_FP64, SCE_SCHEME_KDK,
+ * a stream owned by the context.
+ * Errors: SCE_EINVAL if L <= 0 or non-finite, n_max < 1 or n_max > 64,
+ * shape_width < 0 or non-finite, unknown shape_kind, out == NULL. */
+sce_status sce_create(double L, int32_t n_max, int32_t shape_kind, double shape_width,
+                      sce_ctx *out);
+
+/* eps0 > 0; precision: sce_precision; scheme: sce_scheme; hip_stream: a
+ * hipStream_t on the context's device, or NULL for the context's own stream.
+ * Invalidates cached fields.  SCE_EINVAL on bad values. */
+sce_status sce_set_options(sce_ctx ctx, double eps0, int32_t precision, int32_t scheme,
+                           void *hip_stream);
+
+/* Copy N particles into the context.  x, v: [3][N]; q, m: [N] (m > 0).
+ * Positions outside [0, L) are accepted and wrapped.  Resets the step counter
+ * and the cached force.  SCE_EINVAL if N < 1 or a pointer is NULL. */
+sce_status sce_set_particles(sce_ctx ctx, int64_t N, const double *x, const double *v,
+                             const double *q, const double *m, int32_t on_device);
+
+/* Copy positions and velocities out ([3][N] each; either may be NULL). */
+sce_status sce_get_particles(sce_ctx ctx, double *x, double *v, int32_t on_device);
+
+/* Number of stored half-space modes |H|. */
+sce_status sce_mode_count(sce_ctx ctx, int64_t *n_half);
+
+/* The stored modes in canonical order: nxyz[3*i + d] = n_d of mode i. Host memory. */
+sce_status sce_modes(sce_ctx ctx, int32_t *nxyz);
+
+/* Deposit at the current positions: rho [2 |H|] interleaved (re, im), canonical
+ * mode order, FP64.  rho may be NULL (result kept on the device only). */
+sce_status sce_deposit(sce_ctx ctx, double *rho, int32_t on_device);
+
+/* psi_n = S(k_n) rho_n / (eps0 |k_n|^2 V) from the last deposit, [2 |H|] (re, im). */
+sce_status sce_psi(sce_ctx ctx, double *psi, int32_t on_device);
+
+/* Force at the current positions (deposit, solve, force): F [3][N] FP64.
+ * Velocities are not changed.  F may be NULL. */
+sce_status sce_force(sce_ctx ctx, double *F, int32_t on_device);
+
+/* Advance n_steps >= 0 steps of size dt (finite) with the configured scheme. */
+sce_status sce_step(sce_ctx ctx, double dt, int64_t n_steps);
+
+/* Diagnostics at the current state; rho_abs (|H| doubles, host) may be NULL.
+ * Runs a deposit if the fields are not current.  Returns SCE_EUNSTABLE (with
+ * *out filled) if the energy is not finite. */
+sce_status sce_diagnostics(sce_ctx ctx, sce_diag *out, double *rho_abs);
+
+/* Checkpoint: with buf == NULL, *bytes receives the size needed.  Otherwise
+ * buf (host, *bytes long) receives positions, velocities, charges, masses,
+ * the step counter and the cached force.  SCE_EINVAL if *bytes is too small. */
+sce_status sce_get_state(sce_ctx ctx, void *buf, size_t *bytes);
+
+/* Restore a checkpoint written by sce_get_state for the same L and n_max. */
+sce_status sce_set_state(sce_ctx ctx, const void *buf, size_t bytes);
+
+/* Wait for all work on the context's stream. */
+sce_status sce_sync(sce_ctx ctx);
+
+/* Kernel timing with HIP events recorded on the context's stream.  While
+ * enabled, every launch of the deposit kernel (the particle x mode sum of the
+ * deposit) and of the force kernel (the particle x mode sum of the force, with
+ * its fused kick) is bracketed by a pair of events.  Enabling or disabling
+ * synchronises the stream and clears the totals. */
+sce_status sce_timing_enable(sce_ctx ctx, int32_t enable);
+
+/* Synchronise, then return the summed event time (ms) and launch count of
+ * each kernel since timing was enabled.  Any output pointer may be NULL. */
+sce_status sce_timing_read(sce_ctx ctx, double *deposit_ms, int64_t *deposit_launches,
+                           double *force_ms, int64_t *force_launches);
+
+/* Release the context and its device memory.  NULL is ignored. */
+void sce_destroy(sce_ctx ctx);
+
+const char *sce_status_string(sce_status s);
+
+/* Last error message of this context ("" if none). */
+const char *sce_last_error(sce_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCE_H */

@@ -9,7 +9,9 @@
  * no code, header, table or constant with the HIP library.
  *
  * Every sum here is the plain definition: one cos/sin per (particle, mode)
- * pair, accumulated in index order in double precision.  No separable phase
+ * pair, accumulated in index order in double precision with compensated
+ * (Neumaier) summation, so the reference stays accurate to a few ulps of the
+ * largest partial sum however many particles are summed.  No separable phase
  * tables, no blocking, no reordering.  OpenMP only splits independent outputs
  * (modes for the deposit, particles for the force) across threads; each
  * output's own sum runs serially in index order, so results do not depend on
@@ -90,6 +92,17 @@ double sce_oracle_shape(int32_t kind, double a, double kx, double ky, double kz)
     }
 }
 
+/* Compensated running sum (Neumaier's variant of Kahan summation). */
+typedef struct { double s, c; } csum;
+static void csum_add(csum *a, double x)
+{
+    const double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double csum_get(const csum *a) { return a->s + a->c; }
+
 /* Phase k_n . x_j for mode (nx, ny, nz). */
 static double phase(double L, int nx, int ny, int nz, double x, double y, double z)
 {
@@ -105,16 +118,16 @@ void sce_oracle_deposit(int64_t N, const double *x, const double *y, const doubl
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < n_modes; ++i) {
         const int nx = modes[3 * i], ny = modes[3 * i + 1], nz = modes[3 * i + 2];
-        double re = 0.0, im = 0.0;
+        csum re = {0.0, 0.0}, im = {0.0, 0.0};
         for (int64_t j = 0; j < N; ++j) {
             const double th = phase(L, nx, ny, nz, x[j], y[j], z[j]);
-            re += q[j] * cos(th);
-            im -= q[j] * sin(th);
+            csum_add(&re, q[j] * cos(th));
+            csum_add(&im, -q[j] * sin(th));
         }
         const double f = TWO_PI / L;
         const double s = sce_oracle_shape(kind, a, f * nx, f * ny, f * nz);
-        rho[2 * i] = s * re;
-        rho[2 * i + 1] = s * im;
+        rho[2 * i] = s * csum_get(&re);
+        rho[2 * i + 1] = s * csum_get(&im);
     }
 }
 
@@ -141,19 +154,19 @@ void sce_oracle_force(int64_t N, const double *x, const double *y, const double 
     const double f = TWO_PI / L;
     #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j) {
-        double fx = 0.0, fy = 0.0, fz = 0.0;
+        csum fx = {0.0, 0.0}, fy = {0.0, 0.0}, fz = {0.0, 0.0};
         for (int64_t i = 0; i < n_modes; ++i) {
             const int nx = modes[3 * i], ny = modes[3 * i + 1], nz = modes[3 * i + 2];
             const double th = phase(L, nx, ny, nz, x[j], y[j], z[j]);
             /* Im((pr + i pi)(cos + i sin)) = pr sin + pi cos */
             const double im = psi[2 * i] * sin(th) + psi[2 * i + 1] * cos(th);
-            fx += f * nx * im;
-            fy += f * ny * im;
-            fz += f * nz * im;
+            csum_add(&fx, f * nx * im);
+            csum_add(&fy, f * ny * im);
+            csum_add(&fz, f * nz * im);
         }
-        F[j] = 2.0 * q[j] * fx;
-        F[N + j] = 2.0 * q[j] * fy;
-        F[2 * N + j] = 2.0 * q[j] * fz;
+        F[j] = 2.0 * q[j] * csum_get(&fx);
+        F[N + j] = 2.0 * q[j] * csum_get(&fy);
+        F[2 * N + j] = 2.0 * q[j] * csum_get(&fz);
     }
 }
 
@@ -164,13 +177,13 @@ void sce_oracle_potential(int64_t N, const double *x, const double *y, const dou
 {
     #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j) {
-        double s = 0.0;
+        csum s = {0.0, 0.0};
         for (int64_t i = 0; i < n_modes; ++i) {
             const double th = phase(L, modes[3 * i], modes[3 * i + 1], modes[3 * i + 2],
                                     x[j], y[j], z[j]);
-            s += psi[2 * i] * cos(th) - psi[2 * i + 1] * sin(th);
+            csum_add(&s, psi[2 * i] * cos(th) - psi[2 * i + 1] * sin(th));
         }
-        Phi[j] = 2.0 * s;
+        Phi[j] = 2.0 * csum_get(&s);
     }
 }
 
@@ -179,13 +192,13 @@ double sce_oracle_field_energy(int64_t n_modes, const int32_t *modes, const doub
                                double L, double eps0)
 {
     const double f = TWO_PI / L, V = L * L * L;
-    double s = 0.0;
+    csum s = {0.0, 0.0};
     for (int64_t i = 0; i < n_modes; ++i) {
         const double kx = f * modes[3 * i], ky = f * modes[3 * i + 1], kz = f * modes[3 * i + 2];
         const double k2 = kx * kx + ky * ky + kz * kz;
-        s += (rho[2 * i] * rho[2 * i] + rho[2 * i + 1] * rho[2 * i + 1]) / k2;
+        csum_add(&s, (rho[2 * i] * rho[2 * i] + rho[2 * i + 1] * rho[2 * i + 1]) / k2);
     }
-    return s / (eps0 * V);
+    return csum_get(&s) / (eps0 * V);
 }
 
 /* Number of threads OpenMP will use (reported with the CPU baseline). */

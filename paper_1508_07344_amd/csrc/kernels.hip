@@ -1,0 +1,586 @@
+// Direct (VALU) kernels of the spectral canonical electrostatic hot path on
+// gfx950: per-particle phase tables, the deposit (type-1 nonuniform DFT), the
+// cross-tile reduction with the field solve, the force (type-2 nonuniform
+// DFT) with a fused kick, drift/kick, and FP64 diagnostics.
+//
+// Both particle x mode sums use the paper's separable phases (Section 8: with
+// modes spaced 2 pi / L, each per-mode exponential is an integer power of one
+// exponential per axis), plus the fact that the particle weights are real, so
+// that the +n_z and -n_z modes of a row share cos(n_z theta_z) and
+// sin(n_z theta_z):
+//   deposit  P(r, nz) = sum_j h_j(r) cos(nz tz_j),  Q(r, nz) = sum_j h_j(r) sin(nz tz_j),
+//            h_j(r) = q_j exp(-i (nx tx_j + ny ty_j)),  rho(r, +-nz) = S (P -+ i Q)
+//            -> 2 real FMA per particle x mode.
+//   force    U0(r) = psi(r,0) + sum_{nz>0} (sig cos + i del sin),
+//            U1(r) = sum_{nz>0} nz (del cos + i sig sin),  sig/del = psi(+nz) +- psi(-nz)
+//            F += (nx Im(g U0), ny Im(g U0), Im(g U1)), g = exp(i (nx tx + ny ty))
+//            -> 4 real FMA per particle x mode.
+// Angles are t = x / L in turns; every anchor exp(2 pi i k t) is taken with
+// sincospi on an exactly reduced k t, and runs of at most 8 powers in between
+// use FP64 complex multiplication.
+
+#include "sce_internal.h"
+
+namespace sce {
+
+template <typename T> struct C2;
+template <> struct C2<float> { typedef float2 t; };
+template <> struct C2<double> { typedef double2 t; };
+
+__device__ inline double frac(double t) { return t - floor(t); }
+
+// frac(k t) with the product formed exactly (two-product) before reduction.
+__device__ inline double frac_mul(int k, double t)
+{
+    const double hi = (double)k * t;
+    const double lo = fma((double)k, t, -hi);
+    const double u = (hi - floor(hi)) + lo;
+    return u - floor(u);
+}
+
+// frac(a ta + b tb), each product exact before reduction.
+__device__ inline double frac_lin(int a, double ta, int b, double tb)
+{
+    const double h1 = (double)a * ta, l1 = fma((double)a, ta, -h1);
+    const double h2 = (double)b * tb, l2 = fma((double)b, tb, -h2);
+    const double u = (h1 - floor(h1)) + (h2 - floor(h2)) + (l1 + l2);
+    return u - floor(u);
+}
+
+// (cos, sin)(2 pi u)
+__device__ inline void cis_turns(double u, double &c, double &s) { sincospi(2.0 * u, &s, &c); }
+
+// ------------------------------------------------------------------ phase table
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_phase_table(const double *__restrict__ pos, int64_t N, int n, int zslots, double invL,
+              T *__restrict__ tab)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    T *out = tab + j * (int64_t)(6 * zslots);
+    for (int d = 0; d < 3; ++d) {
+        const double t = frac(pos[d * N + j] * invL);
+        double c1, s1;
+        cis_turns(t, c1, s1);
+        double c = 1.0, s = 0.0;
+        for (int k = 0; k < zslots; ++k) {
+            if (k > n) {
+                c = 0.0;
+                s = 0.0;
+            } else if (k > 0 && (k & 7) == 0) {
+                cis_turns(frac_mul(k, t), c, s);
+            }
+            out[2 * (d * zslots + k)] = (T)c;
+            out[2 * (d * zslots + k) + 1] = (T)s;
+            const double cn = c * c1 - s * s1;
+            s = s * c1 + c * s1;
+            c = cn;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_phase_table(hipStream_t s, const double *pos, int64_t N, const Geom &g,
+                              double L, T *tab)
+{
+    const int64_t blocks = (N + 255) / 256;
+    hipLaunchKernelGGL(k_phase_table<T>, dim3((unsigned)blocks), dim3(256), 0, s, pos, N, g.n,
+                       g.zslots, 1.0 / L, tab);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ deposit
+// Block = 4 waves.  A wave owns 64 rows (one per lane) and one group of ZB
+// n_z values; waves of a block share their rows' h values, staged per chunk of
+// kc particles in LDS.  The per-particle cos/sin of the wave's n_z group are
+// wave-uniform and read with scalar loads.  blockIdx.z selects the particle
+// split whose partial sums the block writes.
+template <typename T, int ZB>
+__global__ void __launch_bounds__(256)
+k_deposit(const T *__restrict__ tab, const double *__restrict__ q, int64_t N, int n, int R,
+          int Rpad, int zslots, int groups, int waves_per_rs, int rows_per_wg, int kc,
+          int64_t per_split, double *__restrict__ part)
+{
+    typedef typename C2<T>::t CT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    CT *hs = reinterpret_cast<CT *>(smem_raw);
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int rs = wave / waves_per_rs;
+    const int group = blockIdx.y * waves_per_rs + (wave - rs * waves_per_rs);
+    const bool active = (rs * 64 < rows_per_wg) && (group < groups);
+    const int row_local = rs * 64 + lane;
+    const int row = blockIdx.x * rows_per_wg + row_local;
+    const int64_t j0 = (int64_t)blockIdx.z * per_split;
+    const int64_t j1 = j0 + per_split < N ? j0 + per_split : N;
+    const int z0 = 1 + group * ZB;
+    const int64_t pstride = 6 * (int64_t)zslots;
+
+    T aP[ZB][2], aQ[ZB][2];
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) aP[k][0] = aP[k][1] = aQ[k][0] = aQ[k][1] = (T)0;
+    T a0r = 0, a0i = 0;
+
+    for (int64_t base = j0; base < j1; base += kc) {
+        const int cnt = (int)((j1 - base) < kc ? (j1 - base) : kc);
+        for (int idx = tid; idx < kc * rows_per_wg; idx += 256) {
+            const int jj = idx / rows_per_wg;
+            const int rl = idx - jj * rows_per_wg;
+            const int r = blockIdx.x * rows_per_wg + rl;
+            CT h;
+            h.x = (T)0;
+            h.y = (T)0;
+            if (jj < cnt && r < R) {
+                int nx, ny;
+                row_nxny(r, n, nx, ny);
+                const T *tj = tab + (base + jj) * pstride;
+                const T cx = tj[2 * nx], sx = -tj[2 * nx + 1];
+                const int ay = ny < 0 ? -ny : ny;
+                const T cy = tj[2 * (zslots + ay)];
+                const T sy = ny < 0 ? tj[2 * (zslots + ay) + 1] : -tj[2 * (zslots + ay) + 1];
+                const T qq = (T)q[base + jj];
+                h.x = qq * (cx * cy - sx * sy);
+                h.y = qq * (cx * sy + sx * cy);
+            }
+            hs[idx] = h;
+        }
+        __syncthreads();
+        if (active) {
+            for (int jj = 0; jj < cnt; ++jj) {
+                const CT h = hs[jj * rows_per_wg + row_local];
+                const T *cs = tab + (base + jj) * pstride + 2 * (2 * zslots + z0);
+#pragma unroll
+                for (int k = 0; k < ZB; ++k) {
+                    const T c = cs[2 * k], s = cs[2 * k + 1];
+                    aP[k][0] = fma(h.x, c, aP[k][0]);
+                    aP[k][1] = fma(h.y, c, aP[k][1]);
+                    aQ[k][0] = fma(h.x, s, aQ[k][0]);
+                    aQ[k][1] = fma(h.y, s, aQ[k][1]);
+                }
+                if (group == 0) {
+                    a0r += h.x;
+                    a0i += h.y;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    if (active && row < R) {
+        double *pb = part + (int64_t)blockIdx.z * (int64_t)(n + 1) * 4 * Rpad + row;
+#pragma unroll
+        for (int k = 0; k < ZB; ++k) {
+            const int nz = z0 + k;
+            if (nz <= n) {
+                pb[(int64_t)(nz * 4 + 0) * Rpad] = (double)aP[k][0];
+                pb[(int64_t)(nz * 4 + 1) * Rpad] = (double)aP[k][1];
+                pb[(int64_t)(nz * 4 + 2) * Rpad] = (double)aQ[k][0];
+                pb[(int64_t)(nz * 4 + 3) * Rpad] = (double)aQ[k][1];
+            }
+        }
+        if (group == 0) {
+            pb[0] = (double)a0r;
+            pb[(int64_t)Rpad] = (double)a0i;
+            pb[(int64_t)2 * Rpad] = 0.0;
+            pb[(int64_t)3 * Rpad] = 0.0;
+        }
+    }
+}
+
+DepositPlan plan_deposit(const Geom &g, int64_t N, int elem_bytes)
+{
+    DepositPlan p;
+    p.zb = g.n <= 4 ? 4 : 8;
+    p.groups = (g.n + p.zb - 1) / p.zb;
+    p.waves_per_rs = p.groups < 4 ? p.groups : 4;
+    const int rowsets = 4 / p.waves_per_rs;
+    p.rows_per_wg = 64 * rowsets;
+    p.grid_y = (p.groups + p.waves_per_rs - 1) / p.waves_per_rs;
+    p.row_blocks = (g.R + p.rows_per_wg - 1) / p.rows_per_wg;
+    // LDS chunk: keep the h tile at 32 KiB
+    p.kc = (32768 / elem_bytes / 2) / p.rows_per_wg;
+    if (p.kc < 4) p.kc = 4;
+    // enough blocks to fill 256 CUs several times over; at least 256 particles per split
+    const int64_t blocks_per_split = (int64_t)p.row_blocks * p.grid_y;
+    int64_t splits = (2048 + blocks_per_split - 1) / blocks_per_split;
+    const int64_t max_splits = N / 256 > 1 ? N / 256 : 1;
+    if (splits > max_splits) splits = max_splits;
+    if (splits > 1024) splits = 1024;
+    if (splits < 1) splits = 1;
+    int64_t per = (N + splits - 1) / splits;
+    per = (per + p.kc - 1) / p.kc * p.kc;
+    p.per_split = per;
+    p.splits = (int)((N + per - 1) / per);
+    return p;
+}
+
+template <typename T>
+hipError_t launch_deposit(hipStream_t s, const T *tab, const double *q, int64_t N, const Geom &g,
+                          const DepositPlan &pl, double *part)
+{
+    typedef typename C2<T>::t CT;
+    const size_t shmem = (size_t)pl.kc * pl.rows_per_wg * sizeof(CT);
+    dim3 grid((unsigned)pl.row_blocks, (unsigned)pl.grid_y, (unsigned)pl.splits);
+    if (pl.zb == 4)
+        hipLaunchKernelGGL((k_deposit<T, 4>), grid, dim3(256), shmem, s, tab, q, N, g.n, g.R,
+                           g.Rpad, g.zslots, pl.groups, pl.waves_per_rs, pl.rows_per_wg, pl.kc,
+                           pl.per_split, part);
+    else
+        hipLaunchKernelGGL((k_deposit<T, 8>), grid, dim3(256), shmem, s, tab, q, N, g.n, g.R,
+                           g.Rpad, g.zslots, pl.groups, pl.waves_per_rs, pl.rows_per_wg, pl.kc,
+                           pl.per_split, part);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ reduce + solve
+__device__ inline double block_sum(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+__device__ inline double block_max(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t = fmax(t, sh[i]);
+    __syncthreads();
+    return t;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_reduce_solve(const double *__restrict__ part, int splits, int n, int R, int Rpad, int nzp,
+               const double *__restrict__ Stab, const double *__restrict__ Gtab,
+               const double *__restrict__ Ktab, double2 *__restrict__ rho,
+               double2 *__restrict__ psi, T *__restrict__ ftab, T *__restrict__ psi0,
+               double *__restrict__ wpart)
+{
+    __shared__ double sh[8];
+    const int n1 = n + 1, M = 2 * n + 1;
+    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double w = 0.0, amax = 0.0;
+    if (cell < (int64_t)n1 * R) {
+        const int nz = (int)(cell / R);
+        const int row = (int)(cell - (int64_t)nz * R);
+        const int64_t sstride = (int64_t)n1 * 4 * Rpad;
+        const double *pp = part + (int64_t)nz * 4 * Rpad + row;
+        double Pr = 0.0, Pi = 0.0, Qr = 0.0, Qi = 0.0;
+        for (int sp = 0; sp < splits; ++sp, pp += sstride) {
+            Pr += pp[0];
+            Pi += pp[Rpad];
+            Qr += pp[2 * (int64_t)Rpad];
+            Qi += pp[3 * (int64_t)Rpad];
+        }
+        int nx, ny;
+        row_nxny(row, n, nx, ny);
+        const double S = Stab[row * n1 + nz], G = Gtab[row * n1 + nz], K = Ktab[row * n1 + nz];
+        const double2 rp = make_double2(S * (Pr + Qi), S * (Pi - Qr));
+        const double2 rm = make_double2(S * (Pr - Qi), S * (Pi + Qr));
+        const bool hp = in_half(nx, ny, nz);
+        const bool hm = nz > 0 && in_half(nx, ny, -nz);
+        const double2 pp_ = hp ? make_double2(G * rp.x, G * rp.y) : make_double2(0.0, 0.0);
+        const double2 pm_ = hm ? make_double2(G * rm.x, G * rm.y) : make_double2(0.0, 0.0);
+        const int64_t rb = (int64_t)row * M + n;
+        rho[rb + nz] = rp;
+        psi[rb + nz] = pp_;
+        if (nz > 0) {
+            rho[rb - nz] = rm;
+            psi[rb - nz] = pm_;
+        }
+        if (hp) {
+            w += K * (rp.x * rp.x + rp.y * rp.y);
+            amax = fmax(amax, sqrt(rp.x * rp.x + rp.y * rp.y));
+        }
+        if (hm) {
+            w += K * (rm.x * rm.x + rm.y * rm.y);
+            amax = fmax(amax, sqrt(rm.x * rm.x + rm.y * rm.y));
+        }
+        if (nz == 0) {
+            psi0[2 * row] = (T)pp_.x;
+            psi0[2 * row + 1] = (T)pp_.y;
+        } else {
+            T *f = ftab + ((int64_t)row * nzp + (nz - 1)) * 8;
+            const double sr = pp_.x + pm_.x, si = pp_.y + pm_.y;
+            const double dr = pp_.x - pm_.x, di = pp_.y - pm_.y;
+            f[0] = (T)sr;
+            f[1] = (T)si;
+            f[2] = (T)dr;
+            f[3] = (T)di;
+            f[4] = (T)(nz * dr);
+            f[5] = (T)(nz * di);
+            f[6] = (T)(nz * sr);
+            f[7] = (T)(nz * si);
+        }
+    }
+    const double ws = block_sum(w, sh);
+    const double wm = block_max(amax, sh);
+    if (threadIdx.x == 0) {
+        wpart[2 * blockIdx.x] = ws;
+        wpart[2 * blockIdx.x + 1] = wm;
+    }
+}
+
+template <typename T>
+hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, const Geom &g,
+                               const double *Stab, const double *Gtab, const double *Ktab,
+                               double2 *rho, double2 *psi, T *ftab, T *psi0, double *wpart,
+                               int *wblocks)
+{
+    const int64_t cells = (int64_t)(g.n + 1) * g.R;
+    const int blocks = (int)((cells + 255) / 256);
+    *wblocks = blocks;
+    hipLaunchKernelGGL(k_reduce_solve<T>, dim3(blocks), dim3(256), 0, s, part, splits, g.n, g.R,
+                       g.Rpad, g.nzp, Stab, Gtab, Ktab, rho, psi, ftab, psi0, wpart);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ force
+// One particle per lane.  Rows are visited in the same order by every lane,
+// so the force table entries of a row are wave-uniform (scalar loads); the
+// lane's cos/sin(n_z tz) for a chunk of NZC values stay in registers.
+template <typename T, int NZC>
+__global__ void __launch_bounds__(256)
+k_force(const double *__restrict__ pos, const double *__restrict__ q,
+        const double *__restrict__ m, double *__restrict__ vel, const T *__restrict__ ftab,
+        const T *__restrict__ psi0, int n, int nzp, double invL, int64_t N, double kick,
+        double *__restrict__ F, double *__restrict__ phi)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t jc = j < N ? j : N - 1;
+    const double tx = frac(pos[jc] * invL);
+    const double ty = frac(pos[N + jc] * invL);
+    const double tz = frac(pos[2 * N + jc] * invL);
+    double eyc, eys;
+    cis_turns(ty, eyc, eys);
+    double ezc, ezs;
+    cis_turns(tz, ezc, ezs);
+    double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
+
+    for (int c0 = 0; c0 < nzp; c0 += NZC) {
+        T cz[NZC], sz[NZC];
+        {
+            double c, s;
+#pragma unroll
+            for (int k = 0; k < NZC; ++k) {
+                if ((k & 7) == 0) {
+                    cis_turns(frac_mul(c0 + 1 + k, tz), c, s);
+                } else {
+                    const double cn = c * ezc - s * ezs;
+                    s = s * ezc + c * ezs;
+                    c = cn;
+                }
+                cz[k] = (T)c;
+                sz[k] = (T)s;
+            }
+        }
+        int r = 0;
+        for (int nx = 0; nx <= n; ++nx) {
+            const int ny0 = nx == 0 ? 0 : -n;
+            double hc, hs;
+            cis_turns(frac_lin(nx, tx, ny0, ty), hc, hs);
+            for (int ny = ny0; ny <= n; ++ny, ++r) {
+                const T *ft = ftab + ((int64_t)r * nzp + c0) * 8;
+                T u0r = (T)0, u0i = (T)0, u1r = (T)0, u1i = (T)0;
+                if (c0 == 0) {
+                    u0r = psi0[2 * r];
+                    u0i = psi0[2 * r + 1];
+                }
+#pragma unroll
+                for (int k = 0; k < NZC; ++k) {
+                    const T c = cz[k], s = sz[k];
+                    u0r = fma(ft[8 * k + 0], c, u0r);
+                    u0i = fma(ft[8 * k + 1], c, u0i);
+                    u0r = fma(-ft[8 * k + 3], s, u0r);
+                    u0i = fma(ft[8 * k + 2], s, u0i);
+                    u1r = fma(ft[8 * k + 4], c, u1r);
+                    u1i = fma(ft[8 * k + 5], c, u1i);
+                    u1r = fma(-ft[8 * k + 7], s, u1r);
+                    u1i = fma(ft[8 * k + 6], s, u1i);
+                }
+                const double im0 = hc * (double)u0i + hs * (double)u0r;
+                const double re0 = hc * (double)u0r - hs * (double)u0i;
+                const double im1 = hc * (double)u1i + hs * (double)u1r;
+                fx = fma((double)nx, im0, fx);
+                fy = fma((double)ny, im0, fy);
+                fz += im1;
+                ph += re0;
+                const double t = hc * eyc - hs * eys;
+                hs = hs * eyc + hc * eys;
+                hc = t;
+            }
+        }
+    }
+    if (j < N) {
+        const double f = 2.0 * q[j] * (6.283185307179586476925286766559 * invL);
+        fx *= f;
+        fy *= f;
+        fz *= f;
+        if (F) {
+            F[j] = fx;
+            F[N + j] = fy;
+            F[2 * N + j] = fz;
+        }
+        if (phi) phi[j] = 2.0 * ph;
+        if (kick != 0.0) {
+            const double a = kick / m[j];
+            vel[j] += a * fx;
+            vel[N + j] += a * fy;
+            vel[2 * N + j] += a * fz;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const double *m,
+                        double *vel, const T *ftab, const T *psi0, const Geom &g, double L,
+                        int64_t N, double kick, double *F, double *phi)
+{
+    const int64_t blocks = (N + 255) / 256;
+    const int nzc = g.nzp <= 8 ? 8 : (g.nzp <= 16 ? 16 : 32);
+    if (nzc == 8)
+        hipLaunchKernelGGL((k_force<T, 8>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
+                           vel, ftab, psi0, g.n, g.nzp, 1.0 / L, N, kick, F, phi);
+    else if (nzc == 16)
+        hipLaunchKernelGGL((k_force<T, 16>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
+                           vel, ftab, psi0, g.n, g.nzp, 1.0 / L, N, kick, F, phi);
+    else
+        hipLaunchKernelGGL((k_force<T, 32>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
+                           vel, ftab, psi0, g.n, g.nzp, 1.0 / L, N, kick, F, phi);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ drift / kick
+__device__ inline double wrap_box(double x, double L, double invL)
+{
+    double w = x - L * floor(x * invL);
+    if (w >= L || w < 0.0) w = 0.0;
+    return w;
+}
+
+__global__ void __launch_bounds__(256)
+k_kick_drift(double *__restrict__ pos, double *__restrict__ vel, const double *__restrict__ F,
+             const double *__restrict__ m, int64_t N, double L, double invL, double a, double b)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    const double am = a != 0.0 ? a / m[j] : 0.0;
+    for (int d = 0; d < 3; ++d) {
+        double v = vel[d * N + j];
+        if (a != 0.0) {
+            v += am * F[d * N + j];
+            vel[d * N + j] = v;
+        }
+        if (b != 0.0) pos[d * N + j] = wrap_box(pos[d * N + j] + b * v, L, invL);
+    }
+}
+
+hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *F,
+                             const double *m, int64_t N, double L, double a, double b)
+{
+    const int64_t blocks = (N + 255) / 256;
+    hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)blocks), dim3(256), 0, s, pos, vel, F, m, N,
+                       L, 1.0 / L, a, b);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256)
+k_wrap(double *__restrict__ pos, int64_t n3, double L, double invL)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n3) pos[i] = wrap_box(pos[i], L, invL);
+}
+
+hipError_t launch_wrap(hipStream_t s, double *pos, int64_t N, double L)
+{
+    const int64_t blocks = (3 * N + 255) / 256;
+    hipLaunchKernelGGL(k_wrap, dim3((unsigned)blocks), dim3(256), 0, s, pos, 3 * N, L, 1.0 / L);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ diagnostics
+// scratch: [blocks][6] partial sums, written in block order.
+__global__ void __launch_bounds__(256)
+k_diag_partial(const double *__restrict__ vel, const double *__restrict__ q,
+               const double *__restrict__ m, const double *__restrict__ phi, int64_t N,
+               double *__restrict__ scratch)
+{
+    __shared__ double sh[8];
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (j < N) {
+        const double vx = vel[j], vy = vel[N + j], vz = vel[2 * N + j], mm = m[j];
+        const double v2 = vx * vx + vy * vy + vz * vz;
+        v[0] = 0.5 * mm * v2;
+        v[1] = mm * vx;
+        v[2] = mm * vy;
+        v[3] = mm * vz;
+        v[4] = mm * sqrt(v2);
+        v[5] = phi ? q[j] * phi[j] : 0.0;
+    }
+    for (int i = 0; i < 6; ++i) {
+        const double t = block_sum(v[i], sh);
+        if (threadIdx.x == 0) scratch[6 * blockIdx.x + i] = t;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_diag_finish(const double *__restrict__ scratch, int nb, const double *__restrict__ wpart,
+              int wb, double *__restrict__ out)
+{
+    __shared__ double sh[8];
+    for (int i = 0; i < 6; ++i) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 256) t += scratch[6 * b + i];
+        t = block_sum(t, sh);
+        if (threadIdx.x == 0) out[i] = t;
+    }
+    double w = 0.0, mx = 0.0;
+    for (int b = threadIdx.x; b < wb; b += 256) {
+        w += wpart[2 * b];
+        mx = fmax(mx, wpart[2 * b + 1]);
+    }
+    w = block_sum(w, sh);
+    mx = block_max(mx, sh);
+    if (threadIdx.x == 0) {
+        out[6] = w;
+        out[7] = mx;
+    }
+}
+
+hipError_t launch_diag(hipStream_t s, const double *vel, const double *q, const double *m,
+                       const double *phi, int64_t N, const double *wpart, int wblocks,
+                       double eps0V, double *scratch, double *out)
+{
+    (void)eps0V;
+    const int nb = (int)((N + 255) / 256);
+    hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(256), 0, s, vel, q, m, phi, N, scratch);
+    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(256), 0, s, scratch, nb, wpart, wblocks, out);
+    return hipGetLastError();
+}
+
+// explicit instantiations
+template hipError_t launch_phase_table<float>(hipStream_t, const double *, int64_t, const Geom &, double, float *);
+template hipError_t launch_phase_table<double>(hipStream_t, const double *, int64_t, const Geom &, double, double *);
+template hipError_t launch_deposit<float>(hipStream_t, const float *, const double *, int64_t, const Geom &, const DepositPlan &, double *);
+template hipError_t launch_deposit<double>(hipStream_t, const double *, const double *, int64_t, const Geom &, const DepositPlan &, double *);
+template hipError_t launch_reduce_solve<float>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, float *, float *, double *, int *);
+template hipError_t launch_reduce_solve<double>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, double *, double *, double *, int *);
+template hipError_t launch_force<float>(hipStream_t, const double *, const double *, const double *, double *, const float *, const float *, const Geom &, double, int64_t, double, double *, double *);
+template hipError_t launch_force<double>(hipStream_t, const double *, const double *, const double *, double *, const double *, const double *, const Geom &, double, int64_t, double, double *, double *);
+
+}  // namespace sce

@@ -1,0 +1,729 @@
+// Host runtime and C ABI of the spectral canonical electrostatic library.
+// Owns the device buffers of a context, builds the mode tables, and orders
+// the kernels of one pass (phase table -> deposit -> reduce/solve -> force)
+// and of the leapfrog steps on the context's HIP stream.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sce.h"
+#include "sce_internal.h"
+
+using sce::Geom;
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+struct EventPair {
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct sce_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool broken = false;
+
+    double L = 1.0, width = 0.0, eps0 = 1.0;
+    int kind = SCE_SHAPE_GAUSSIAN;
+    int prec = SCE_PREC_FP64;
+    int scheme = SCE_SCHEME_KDK;
+    Geom g{};
+
+    int64_t N = 0, cap = 0;
+    double *pos = nullptr, *vel = nullptr, *q = nullptr, *m = nullptr, *F = nullptr,
+           *phi = nullptr;
+    void *tab = nullptr;
+    size_t tab_bytes = 0;
+    double *part = nullptr;
+    size_t part_bytes = 0;
+    double *Stab = nullptr, *Gtab = nullptr, *Ktab = nullptr;
+    double2 *rho = nullptr, *psi = nullptr;
+    void *ftab = nullptr, *psi0 = nullptr;
+    double *wpart = nullptr;
+    int wblocks = 0;
+    double *dscratch = nullptr;
+    size_t dscratch_bytes = 0;
+    double *dout = nullptr;
+
+    bool fields_valid = false;  // rho/psi/W/ftab correspond to the current positions
+    bool force_valid = false;   // F/phi correspond to the current positions
+    int64_t step = 0;
+    double time = 0.0;
+    double q2sum = 0.0;
+    double self_sum = 0.0;  // sum_H S^2 / |k|^2
+
+    bool timing = false;
+    std::vector<EventPair> ev_dep, ev_frc;
+    std::vector<hipEvent_t> ev_pool;
+
+    std::string err;
+};
+
+namespace {
+
+sce_status fail(sce_ctx c, sce_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+sce_status hipfail(sce_ctx c, hipError_t e, const char *what)
+{
+    if (c) {
+        c->broken = true;
+        c->err = std::string(what) + ": " + hipGetErrorString(e);
+    }
+    return SCE_EDEVICE;
+}
+
+#define HIPCHK(c, expr)                                   \
+    do {                                                  \
+        hipError_t _e = (expr);                           \
+        if (_e != hipSuccess) return hipfail(c, _e, #expr); \
+    } while (0)
+
+int force_chunk(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : 32); }
+
+Geom make_geom(int n)
+{
+    Geom g;
+    g.n = n;
+    g.M = 2 * n + 1;
+    g.n1 = n + 1;
+    g.R = (n + 1) + n * g.M;
+    g.Rpad = (g.R + 63) / 64 * 64;
+    g.P = (int64_t)g.R * g.M;
+    g.H = g.P - (n + 1);
+    const int c = force_chunk(n);
+    g.nzp = (n + c - 1) / c * c;
+    const int zb = n <= 4 ? 4 : 8;
+    const int groups = (n + zb - 1) / zb;
+    g.zslots = 1 + groups * zb;
+    return g;
+}
+
+double shape_factor(int kind, double a, double kx, double ky, double kz)
+{
+    if (kind == SCE_SHAPE_DELTA) return 1.0;
+    if (kind == SCE_SHAPE_GAUSSIAN) return std::exp(-0.5 * (kx * kx + ky * ky + kz * kz) * a * a);
+    auto sinc = [](double u) { return u == 0.0 ? 1.0 : std::sin(u) / u; };
+    const double sx = sinc(0.5 * kx * a), sy = sinc(0.5 * ky * a), sz = sinc(0.5 * kz * a);
+    return sx * sx * sy * sy * sz * sz;
+}
+
+size_t elem_bytes(int prec) { return prec == SCE_PREC_FP64 ? 8 : 4; }
+
+void free_dev(void *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+template <typename T>
+void free_devp(T *&p)
+{
+    void *v = p;
+    free_dev(v);
+    p = nullptr;
+}
+
+template <typename T>
+hipError_t dev_alloc(T *&p, size_t bytes)
+{
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
+    p = (T *)v;
+    return e;
+}
+
+// Green tables for (row, |n_z|): S, G = S / (eps0 k^2 V), K = 1 / (eps0 k^2 V).
+sce_status build_tables(sce_ctx c)
+{
+    const Geom &g = c->g;
+    const size_t cnt = (size_t)g.R * g.n1;
+    std::vector<double> S(cnt), G(cnt), K(cnt);
+    const double f = kTwoPi / c->L, V = c->L * c->L * c->L;
+    double self = 0.0;
+    for (int r = 0; r < g.R; ++r) {
+        int nx, ny;
+        sce::row_nxny(r, g.n, nx, ny);
+        for (int nz = 0; nz <= g.n; ++nz) {
+            const size_t i = (size_t)r * g.n1 + nz;
+            if (nx == 0 && ny == 0 && nz == 0) {
+                S[i] = G[i] = K[i] = 0.0;
+                continue;
+            }
+            const double kx = f * nx, ky = f * ny, kz = f * nz;
+            const double k2 = kx * kx + ky * ky + kz * kz;
+            const double s = shape_factor(c->kind, c->width, kx, ky, kz);
+            S[i] = s;
+            K[i] = 1.0 / (c->eps0 * k2 * V);
+            G[i] = s * K[i];
+            const int mult = (sce::in_half(nx, ny, nz) ? 1 : 0) +
+                             ((nz > 0 && sce::in_half(nx, ny, -nz)) ? 1 : 0);
+            self += mult * s * s / k2;
+        }
+    }
+    c->self_sum = self;
+    if (!c->Stab) {
+        HIPCHK(c, dev_alloc(c->Stab, cnt * sizeof(double)));
+        HIPCHK(c, dev_alloc(c->Gtab, cnt * sizeof(double)));
+        HIPCHK(c, dev_alloc(c->Ktab, cnt * sizeof(double)));
+    }
+    HIPCHK(c, hipMemcpy(c->Stab, S.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->Gtab, G.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->Ktab, K.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+    return SCE_OK;
+}
+
+// Buffers whose size depends on the precision (force table, psi0).
+sce_status alloc_prec_buffers(sce_ctx c)
+{
+    free_dev(c->ftab);
+    free_dev(c->psi0);
+    const size_t eb = elem_bytes(c->prec == SCE_PREC_FP64 ? SCE_PREC_FP64 : SCE_PREC_FP32);
+    const size_t fbytes = (size_t)c->g.R * c->g.nzp * 8 * eb;
+    HIPCHK(c, hipMalloc(&c->ftab, fbytes));
+    HIPCHK(c, hipMemset(c->ftab, 0, fbytes));
+    HIPCHK(c, hipMalloc(&c->psi0, (size_t)c->g.R * 2 * eb));
+    return SCE_OK;
+}
+
+sce_status ensure_particle_buffers(sce_ctx c, int64_t N)
+{
+    if (N <= c->cap) return SCE_OK;
+    free_devp(c->pos);
+    free_devp(c->vel);
+    free_devp(c->q);
+    free_devp(c->m);
+    free_devp(c->F);
+    free_devp(c->phi);
+    HIPCHK(c, dev_alloc(c->pos, 3 * N * sizeof(double)));
+    HIPCHK(c, dev_alloc(c->vel, 3 * N * sizeof(double)));
+    HIPCHK(c, dev_alloc(c->q, N * sizeof(double)));
+    HIPCHK(c, dev_alloc(c->m, N * sizeof(double)));
+    HIPCHK(c, dev_alloc(c->F, 3 * N * sizeof(double)));
+    HIPCHK(c, dev_alloc(c->phi, N * sizeof(double)));
+    c->cap = N;
+    return SCE_OK;
+}
+
+sce_status ensure_bytes(sce_ctx c, void *&p, size_t &have, size_t need)
+{
+    if (need <= have) return SCE_OK;
+    free_dev(p);
+    have = 0;
+    HIPCHK(c, hipMalloc(&p, need));
+    have = need;
+    return SCE_OK;
+}
+
+hipEvent_t take_event(sce_ctx c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <typename T>
+sce_status run_deposit(sce_ctx c)
+{
+    const Geom &g = c->g;
+    const sce::DepositPlan pl = sce::plan_deposit(g, c->N, (int)sizeof(T));
+    sce_status st = ensure_bytes(c, c->tab, c->tab_bytes, (size_t)c->N * 6 * g.zslots * sizeof(T));
+    if (st) return st;
+    size_t pb = c->part_bytes;
+    void *pp = c->part;
+    st = ensure_bytes(c, pp, pb, (size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(double));
+    c->part = (double *)pp;
+    c->part_bytes = pb;
+    if (st) return st;
+    HIPCHK(c, sce::launch_phase_table<T>(c->stream, c->pos, c->N, g, c->L, (T *)c->tab));
+    EventPair ep{nullptr, nullptr};
+    if (c->timing) {
+        ep.a = take_event(c);
+        ep.b = take_event(c);
+        if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
+    }
+    HIPCHK(c, sce::launch_deposit<T>(c->stream, (const T *)c->tab, c->q, c->N, g, pl, c->part));
+    if (c->timing && ep.a && ep.b) {
+        HIPCHK(c, hipEventRecord(ep.b, c->stream));
+        c->ev_dep.push_back(ep);
+    }
+    HIPCHK(c, sce::launch_reduce_solve<T>(c->stream, c->part, pl.splits, g, c->Stab, c->Gtab,
+                                          c->Ktab, c->rho, c->psi, (T *)c->ftab, (T *)c->psi0,
+                                          c->wpart, &c->wblocks));
+    c->fields_valid = true;
+    return SCE_OK;
+}
+
+template <typename T>
+sce_status run_force(sce_ctx c, double kick)
+{
+    EventPair ep{nullptr, nullptr};
+    if (c->timing) {
+        ep.a = take_event(c);
+        ep.b = take_event(c);
+        if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
+    }
+    HIPCHK(c, sce::launch_force<T>(c->stream, c->pos, c->q, c->m, c->vel, (const T *)c->ftab,
+                                   (const T *)c->psi0, c->g, c->L, c->N, kick, c->F, c->phi));
+    if (c->timing && ep.a && ep.b) {
+        HIPCHK(c, hipEventRecord(ep.b, c->stream));
+        c->ev_frc.push_back(ep);
+    }
+    c->force_valid = true;
+    return SCE_OK;
+}
+
+sce_status deposit(sce_ctx c)
+{
+    if (c->prec == SCE_PREC_FP64) return run_deposit<double>(c);
+    if (c->prec == SCE_PREC_FP32) return run_deposit<float>(c);
+    return fail(c, SCE_ENOTSUP, "precision not available");
+}
+
+sce_status force(sce_ctx c, double kick)
+{
+    if (c->prec == SCE_PREC_FP64) return run_force<double>(c, kick);
+    if (c->prec == SCE_PREC_FP32) return run_force<float>(c, kick);
+    return fail(c, SCE_ENOTSUP, "precision not available");
+}
+
+// One pass of the hot path at the current positions: deposit, solve, force (+kick).
+sce_status pass(sce_ctx c, double kick)
+{
+    sce_status st = deposit(c);
+    if (st) return st;
+    return force(c, kick);
+}
+
+sce_status check_ready(sce_ctx c)
+{
+    if (!c) return SCE_EINVAL;
+    if (c->broken) return fail(c, SCE_EDEVICE, "context unusable after a device error: " + c->err);
+    HIPCHK(c, hipSetDevice(c->device));
+    return SCE_OK;
+}
+
+sce_status copy_in(sce_ctx c, double *dst, const double *src, size_t bytes, int on_device)
+{
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             c->stream));
+    if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SCE_OK;
+}
+
+sce_status copy_out(sce_ctx c, double *dst, const double *src, size_t bytes, int on_device)
+{
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+    if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SCE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sce_status_string(sce_status s)
+{
+    switch (s) {
+    case SCE_OK: return "ok";
+    case SCE_EINVAL: return "invalid argument";
+    case SCE_ENOMEM: return "out of memory";
+    case SCE_EDEVICE: return "device error";
+    case SCE_ESTATE: return "invalid state";
+    case SCE_ENOTSUP: return "not supported";
+    case SCE_EUNSTABLE: return "unstable (non-finite energy)";
+    }
+    return "unknown status";
+}
+
+const char *sce_last_error(sce_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+sce_status sce_create(double L, int32_t n_max, int32_t shape_kind, double shape_width, sce_ctx *out)
+{
+    if (!out) return SCE_EINVAL;
+    *out = nullptr;
+    if (!(L > 0.0) || !std::isfinite(L)) return SCE_EINVAL;
+    if (n_max < 1 || n_max > 64) return SCE_EINVAL;
+    if (shape_kind < SCE_SHAPE_DELTA || shape_kind > SCE_SHAPE_TENT) return SCE_EINVAL;
+    if (!(shape_width >= 0.0) || !std::isfinite(shape_width)) return SCE_EINVAL;
+    sce_ctx c = new (std::nothrow) sce_ctx_s();
+    if (!c) return SCE_ENOMEM;
+    c->L = L;
+    c->kind = shape_kind;
+    c->width = shape_width;
+    c->g = make_geom(n_max);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        return SCE_EDEVICE;
+    }
+    c->own_stream = true;
+    sce_status st = build_tables(c);
+    if (!st) {
+        const Geom &g = c->g;
+        if (dev_alloc(c->rho, g.P * sizeof(double2)) != hipSuccess ||
+            dev_alloc(c->psi, g.P * sizeof(double2)) != hipSuccess ||
+            dev_alloc(c->wpart, ((size_t)g.n1 * g.R / 256 + 2) * 2 * sizeof(double)) != hipSuccess ||
+            dev_alloc(c->dout, 8 * sizeof(double)) != hipSuccess)
+            st = SCE_ENOMEM;
+    }
+    if (!st) st = alloc_prec_buffers(c);
+    if (st) {
+        sce_destroy(c);
+        return st;
+    }
+    *out = c;
+    return SCE_OK;
+}
+
+sce_status sce_set_options(sce_ctx c, double eps0, int32_t precision, int32_t scheme, void *hip_stream)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (!(eps0 > 0.0) || !std::isfinite(eps0)) return fail(c, SCE_EINVAL, "eps0 must be finite and > 0");
+    if (precision < SCE_PREC_FP64 || precision > SCE_PREC_SPLIT_F16)
+        return fail(c, SCE_EINVAL, "unknown precision");
+    if (precision == SCE_PREC_SPLIT_F16) return fail(c, SCE_ENOTSUP, "split-precision path not built");
+    if (scheme != SCE_SCHEME_KDK && scheme != SCE_SCHEME_DKD) return fail(c, SCE_EINVAL, "unknown scheme");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const bool prec_changed = precision != c->prec;
+    const bool eps_changed = eps0 != c->eps0;
+    c->eps0 = eps0;
+    c->prec = precision;
+    c->scheme = scheme;
+    if (hip_stream) {
+        if (c->own_stream) HIPCHK(c, hipStreamDestroy(c->stream));
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    }
+    if (eps_changed) {
+        st = build_tables(c);
+        if (st) return st;
+    }
+    if (prec_changed) {
+        st = alloc_prec_buffers(c);
+        if (st) return st;
+        free_dev(c->tab);
+        c->tab_bytes = 0;
+    }
+    c->fields_valid = c->force_valid = false;
+    return SCE_OK;
+}
+
+sce_status sce_set_particles(sce_ctx c, int64_t N, const double *x, const double *v,
+                             const double *q, const double *m, int32_t on_device)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (N < 1) return fail(c, SCE_EINVAL, "N must be >= 1");
+    if (!x || !v || !q || !m) return fail(c, SCE_EINVAL, "NULL particle array");
+    st = ensure_particle_buffers(c, N);
+    if (st) return st;
+    c->N = N;
+    if ((st = copy_in(c, c->pos, x, 3 * N * sizeof(double), on_device))) return st;
+    if ((st = copy_in(c, c->vel, v, 3 * N * sizeof(double), on_device))) return st;
+    if ((st = copy_in(c, c->q, q, N * sizeof(double), on_device))) return st;
+    if ((st = copy_in(c, c->m, m, N * sizeof(double), on_device))) return st;
+    HIPCHK(c, sce::launch_wrap(c->stream, c->pos, N, c->L));
+    // sum q^2 for the self-energy (host copy of q)
+    std::vector<double> hq(N);
+    HIPCHK(c, hipMemcpyAsync(hq.data(), c->q, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double s = 0.0;
+    for (double v_ : hq) s += v_ * v_;
+    c->q2sum = s;
+    c->step = 0;
+    c->time = 0.0;
+    c->fields_valid = c->force_valid = false;
+    return SCE_OK;
+}
+
+sce_status sce_get_particles(sce_ctx c, double *x, double *v, int32_t on_device)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
+    if (x && (st = copy_out(c, x, c->pos, 3 * c->N * sizeof(double), on_device))) return st;
+    if (v && (st = copy_out(c, v, c->vel, 3 * c->N * sizeof(double), on_device))) return st;
+    return SCE_OK;
+}
+
+sce_status sce_mode_count(sce_ctx c, int64_t *n_half)
+{
+    if (!c || !n_half) return SCE_EINVAL;
+    *n_half = c->g.H;
+    return SCE_OK;
+}
+
+sce_status sce_modes(sce_ctx c, int32_t *nxyz)
+{
+    if (!c || !nxyz) return SCE_EINVAL;
+    const Geom &g = c->g;
+    int64_t i = 0;
+    for (int r = 0; r < g.R; ++r) {
+        int nx, ny;
+        sce::row_nxny(r, g.n, nx, ny);
+        for (int nz = -g.n; nz <= g.n; ++nz) {
+            if (!sce::in_half(nx, ny, nz)) continue;
+            nxyz[3 * i] = nx;
+            nxyz[3 * i + 1] = ny;
+            nxyz[3 * i + 2] = nz;
+            ++i;
+        }
+    }
+    return i == g.H ? SCE_OK : fail(c, SCE_EDEVICE, "mode count mismatch");
+}
+
+sce_status sce_deposit(sce_ctx c, double *rho, int32_t on_device)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
+    if ((st = deposit(c))) return st;
+    if (rho) return copy_out(c, rho, (const double *)(c->rho + c->g.n1), c->g.H * sizeof(double2), on_device);
+    return SCE_OK;
+}
+
+sce_status sce_psi(sce_ctx c, double *psi, int32_t on_device)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (!c->fields_valid) return fail(c, SCE_ESTATE, "no current deposit");
+    if (!psi) return fail(c, SCE_EINVAL, "NULL psi");
+    return copy_out(c, psi, (const double *)(c->psi + c->g.n1), c->g.H * sizeof(double2), on_device);
+}
+
+sce_status sce_force(sce_ctx c, double *F, int32_t on_device)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
+    if ((st = pass(c, 0.0))) return st;
+    if (F) return copy_out(c, F, c->F, 3 * c->N * sizeof(double), on_device);
+    return SCE_OK;
+}
+
+sce_status sce_step(sce_ctx c, double dt, int64_t n_steps)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
+    if (!std::isfinite(dt)) return fail(c, SCE_EINVAL, "dt must be finite");
+    if (n_steps < 0) return fail(c, SCE_EINVAL, "n_steps must be >= 0");
+    for (int64_t s = 0; s < n_steps; ++s) {
+        if (c->scheme == SCE_SCHEME_KDK) {
+            if (!c->force_valid && (st = pass(c, 0.0))) return st;
+            HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
+                                             0.5 * dt, dt));
+            c->fields_valid = c->force_valid = false;
+            if ((st = pass(c, 0.5 * dt))) return st;
+        } else {
+            HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
+                                             0.0, 0.5 * dt));
+            if ((st = pass(c, dt))) return st;
+            HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
+                                             0.0, 0.5 * dt));
+            c->fields_valid = c->force_valid = false;
+        }
+        c->step += 1;
+        c->time += dt;
+    }
+    return SCE_OK;
+}
+
+sce_status sce_diagnostics(sce_ctx c, sce_diag *out, double *rho_abs)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (!out) return fail(c, SCE_EINVAL, "NULL output");
+    if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
+    if (!(c->force_valid && c->fields_valid) && (st = pass(c, 0.0))) return st;
+    const int nb = (int)((c->N + 255) / 256);
+    void *ds = c->dscratch;
+    st = ensure_bytes(c, ds, c->dscratch_bytes, (size_t)nb * 6 * sizeof(double));
+    c->dscratch = (double *)ds;
+    if (st) return st;
+    HIPCHK(c, sce::launch_diag(c->stream, c->vel, c->q, c->m, c->phi, c->N, c->wpart, c->wblocks,
+                               c->eps0 * c->L * c->L * c->L, c->dscratch, c->dout));
+    double h[8];
+    HIPCHK(c, hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out->step = c->step;
+    out->time = c->time;
+    out->kinetic = h[0];
+    out->momentum[0] = h[1];
+    out->momentum[1] = h[2];
+    out->momentum[2] = h[3];
+    out->momentum_abs_sum = h[4];
+    out->interaction = h[5];
+    out->field = h[6];
+    out->rho_abs_max = h[7];
+    out->field_self = c->q2sum / (c->eps0 * c->L * c->L * c->L) * c->self_sum;
+    out->total = out->kinetic + out->field;
+    if (rho_abs) {
+        std::vector<double2> r(c->g.H);
+        HIPCHK(c, hipMemcpyAsync(r.data(), c->rho + c->g.n1, c->g.H * sizeof(double2),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < c->g.H; ++i) rho_abs[i] = std::hypot(r[i].x, r[i].y);
+    }
+    if (!std::isfinite(out->total)) return fail(c, SCE_EUNSTABLE, "non-finite energy");
+    return SCE_OK;
+}
+
+namespace {
+struct StateHeader {
+    uint64_t magic;
+    int64_t N;
+    int64_t step;
+    double time;
+    double L;
+    int32_t n_max;
+    int32_t has_force;
+};
+const uint64_t kMagic = 0x31454353484b5053ull;  // "SPKHSCE1"
+}  // namespace
+
+sce_status sce_get_state(sce_ctx c, void *buf, size_t *bytes)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (!bytes) return fail(c, SCE_EINVAL, "NULL size");
+    if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
+    const size_t need = sizeof(StateHeader) + (size_t)c->N * 11 * sizeof(double);
+    if (!buf) {
+        *bytes = need;
+        return SCE_OK;
+    }
+    if (*bytes < need) return fail(c, SCE_EINVAL, "buffer too small");
+    StateHeader hd{kMagic, c->N, c->step, c->time, c->L, c->g.n, c->force_valid ? 1 : 0};
+    std::memcpy(buf, &hd, sizeof(hd));
+    double *d = (double *)((char *)buf + sizeof(hd));
+    const size_t n3 = 3 * c->N * sizeof(double), n1 = c->N * sizeof(double);
+    HIPCHK(c, hipMemcpyAsync(d, c->pos, n3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + 3 * c->N, c->vel, n3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + 6 * c->N, c->q, n1, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + 7 * c->N, c->m, n1, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d + 8 * c->N, c->F, n3, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *bytes = need;
+    return SCE_OK;
+}
+
+sce_status sce_set_state(sce_ctx c, const void *buf, size_t bytes)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (!buf || bytes < sizeof(StateHeader)) return fail(c, SCE_EINVAL, "bad checkpoint");
+    StateHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (hd.magic != kMagic || hd.N < 1 || hd.L != c->L || hd.n_max != c->g.n ||
+        bytes < sizeof(hd) + (size_t)hd.N * 11 * sizeof(double))
+        return fail(c, SCE_EINVAL, "checkpoint does not match this context");
+    const double *d = (const double *)((const char *)buf + sizeof(hd));
+    const int64_t N = hd.N;
+    if ((st = sce_set_particles(c, N, d, d + 3 * N, d + 6 * N, d + 7 * N, 0))) return st;
+    if (hd.has_force) {
+        if ((st = copy_in(c, c->F, d + 8 * N, 3 * N * sizeof(double), 0))) return st;
+        c->force_valid = true;
+    }
+    c->step = hd.step;
+    c->time = hd.time;
+    return SCE_OK;
+}
+
+sce_status sce_sync(sce_ctx c)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SCE_OK;
+}
+
+sce_status sce_timing_enable(sce_ctx c, int32_t enable)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->ev_dep) { c->ev_pool.push_back(p.a); c->ev_pool.push_back(p.b); }
+    for (auto &p : c->ev_frc) { c->ev_pool.push_back(p.a); c->ev_pool.push_back(p.b); }
+    c->ev_dep.clear();
+    c->ev_frc.clear();
+    c->timing = enable != 0;
+    return SCE_OK;
+}
+
+sce_status sce_timing_read(sce_ctx c, double *deposit_ms, int64_t *deposit_launches,
+                           double *force_ms, int64_t *force_launches)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double td = 0.0, tf = 0.0;
+    for (auto &p : c->ev_dep) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, p.a, p.b));
+        td += ms;
+    }
+    for (auto &p : c->ev_frc) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, p.a, p.b));
+        tf += ms;
+    }
+    if (deposit_ms) *deposit_ms = td;
+    if (force_ms) *force_ms = tf;
+    if (deposit_launches) *deposit_launches = (int64_t)c->ev_dep.size();
+    if (force_launches) *force_launches = (int64_t)c->ev_frc.size();
+    return SCE_OK;
+}
+
+void sce_destroy(sce_ctx c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto &p : c->ev_dep) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto &p : c->ev_frc) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    free_devp(c->pos);
+    free_devp(c->vel);
+    free_devp(c->q);
+    free_devp(c->m);
+    free_devp(c->F);
+    free_devp(c->phi);
+    free_dev(c->tab);
+    free_devp(c->part);
+    free_devp(c->Stab);
+    free_devp(c->Gtab);
+    free_devp(c->Ktab);
+    free_devp(c->rho);
+    free_devp(c->psi);
+    free_dev(c->ftab);
+    free_dev(c->psi0);
+    free_devp(c->wpart);
+    free_devp(c->dscratch);
+    free_devp(c->dout);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

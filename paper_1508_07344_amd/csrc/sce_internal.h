@@ -1,0 +1,103 @@
+// Internal declarations shared by the HIP kernels and the host runtime of the
+// spectral canonical electrostatic library (gfx950).
+//
+// Mode layout in HBM ("row layout").  The stored half space H is covered by
+// rows r = (n_x, n_y) and a full n_z line per row:
+//   rows 0..n        : n_x = 0, n_y = r            (n_y < 0 at n_x = 0 lies in -H)
+//   rows n+1..R-1    : n_x = 1 + (r-n-1) / M, n_y = (r-n-1) % M - n
+//   R = (n+1) + n M, M = 2n+1; padded mode p = r M + (n_z + n), P = R M.
+// Row 0 holds n_z = -n..0, which are not in H (0 and the negatives of row 0's
+// positive half); everything else is in H, so the canonical mode index is
+// simply p - (n+1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sce {
+
+struct Geom {
+    int n;       // n_max
+    int M;       // 2n+1
+    int n1;      // n+1
+    int R;       // rows
+    int Rpad;    // rows rounded up to 64
+    int64_t P;   // padded modes R*M
+    int64_t H;   // |H| = P - (n+1)
+    int nzp;     // n_z slots of the force table (n rounded up to the force chunk)
+    int zslots;  // n_z slots (0..zslots-1) of the per-particle phase table, >= n+1
+};
+
+__host__ __device__ inline void row_nxny(int r, int n, int &nx, int &ny)
+{
+    if (r <= n) { nx = 0; ny = r; return; }
+    const int rr = r - (n + 1), M = 2 * n + 1;
+    nx = 1 + rr / M;
+    ny = rr % M - n;
+}
+
+__host__ __device__ inline bool in_half(int nx, int ny, int nz)
+{
+    return nx > 0 || (nx == 0 && (ny > 0 || (ny == 0 && nz > 0)));
+}
+
+// Kernel launchers (kernels.hip).  All return hipError_t of the launch.
+// Precision-templated launchers take T = float or double.
+
+// Per-particle phase table tab[j][3][zslots] of complex T: (cos, sin)(k theta_d)
+// for k = 0..n (k <= n) and zeros up to zslots, theta_d = 2 pi x_d / L.
+template <typename T>
+hipError_t launch_phase_table(hipStream_t s, const double *pos, int64_t N, const Geom &g,
+                              double L, T *tab);
+
+// Deposit partial sums for one particle split per blockIdx.z.  part layout
+// [split][n_z in 0..n][4][Rpad] doubles: (P_re, P_im, Q_re, Q_im) with
+// P = sum q e^{-i(nx tx + ny ty)} cos(nz tz), Q = same with sin.
+struct DepositPlan {
+    int zb;             // n_z per wave group
+    int groups;         // ceil(n / zb)
+    int waves_per_rs;   // waves sharing one 64-row set
+    int rows_per_wg;    // 64 * row sets
+    int grid_y;         // ceil(groups / waves_per_rs)
+    int row_blocks;     // ceil(R / rows_per_wg)
+    int kc;             // particles per LDS chunk
+    int splits;
+    int64_t per_split;
+};
+DepositPlan plan_deposit(const Geom &g, int64_t N, int elem_bytes);
+template <typename T>
+hipError_t launch_deposit(hipStream_t s, const T *tab, const double *q, int64_t N, const Geom &g,
+                          const DepositPlan &pl, double *part);
+
+// Sum the partials over splits in fixed order, form rho and psi on the padded
+// layout, the force table and the per-block (W, max|rho|) partials.
+// ftab layout [R][nzp][8] of T: (sig_re, sig_im, del_re, del_im, nz del_re,
+// nz del_im, nz sig_re, nz sig_im) for n_z = 1..nzp with sig = psi(+nz) + psi(-nz),
+// del = psi(+nz) - psi(-nz); psi0 [R][2]: psi at n_z = 0.
+template <typename T>
+hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, const Geom &g,
+                               const double *Stab, const double *Gtab, const double *Ktab,
+                               double2 *rho, double2 *psi, T *ftab, T *psi0, double *wpart,
+                               int *wblocks);
+
+// Force (and potential) at the current positions; optional kick v += kick F/m.
+template <typename T>
+hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const double *m,
+                        double *vel, const T *ftab, const T *psi0, const Geom &g, double L,
+                        int64_t N, double kick, double *F, double *phi);
+
+// v += a F/m (if a != 0); x = wrap(x + b v) (if b != 0).
+hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *F,
+                             const double *m, int64_t N, double L, double a, double b);
+
+// Wrap positions into [0, L).
+hipError_t launch_wrap(hipStream_t s, double *pos, int64_t N, double L);
+
+// Diagnostics: per-block partial sums then a single-block fixed-order finish.
+// out[0] = K, out[1..3] = P, out[4] = sum m|v|, out[5] = sum q phi,
+// out[6] = W, out[7] = max|rho|.
+hipError_t launch_diag(hipStream_t s, const double *vel, const double *q, const double *m,
+                       const double *phi, int64_t N, const double *wpart, int wblocks,
+                       double eps0V, double *scratch, double *out);
+
+}  // namespace sce

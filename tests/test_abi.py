@@ -1,0 +1,66 @@
+"""Host-side checks of the C ABI: the library loads, exports every function the
+header declares, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1508_07344_amd as sce
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    if not os.path.exists(sce.library_path()):
+        pytest.skip("libsce.so not built")
+    return sce.load_library()
+
+
+def test_header_declares_the_api():
+    names = sce.exported_symbols()
+    for required in ("sce_create", "sce_set_options", "sce_set_particles", "sce_get_particles",
+                     "sce_mode_count", "sce_modes", "sce_deposit", "sce_psi", "sce_force",
+                     "sce_step", "sce_diagnostics", "sce_get_state", "sce_set_state", "sce_sync",
+                     "sce_timing_enable", "sce_timing_read", "sce_destroy", "sce_status_string",
+                     "sce_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    _lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", sce.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sce_\w+)", out))
+    missing = set(sce.exported_symbols()) - exported
+    assert not missing, missing
+    lib = ctypes.CDLL(sce.library_path())
+    for name in sce.exported_symbols():
+        assert hasattr(lib, name)
+
+
+def test_invalid_create_arguments_are_rejected_on_host():
+    lib = _lib()
+    h = ctypes.c_void_p()
+    bad = [(-1.0, 8, 1, 0.05), (float("nan"), 8, 1, 0.05), (float("inf"), 8, 1, 0.05),
+           (1.0, 0, 1, 0.05), (1.0, 65, 1, 0.05), (1.0, 8, 7, 0.05), (1.0, 8, 1, -0.1),
+           (1.0, 8, 1, float("nan"))]
+    for args in bad:
+        assert lib.sce_create(*args, ctypes.byref(h)) == sce.SCE_EINVAL, args
+        assert not h.value
+    assert lib.sce_create(1.0, 8, 1, 0.05, None) == sce.SCE_EINVAL
+
+
+def test_null_context_is_rejected():
+    lib = _lib()
+    assert lib.sce_sync(None) == sce.SCE_EINVAL
+    assert lib.sce_step(None, 1e-3, 1) == sce.SCE_EINVAL
+    assert lib.sce_deposit(None, None, 0) == sce.SCE_EINVAL
+    lib.sce_destroy(None)  # no-op
+
+
+def test_status_strings():
+    lib = _lib()
+    for s in range(-6, 1):
+        assert lib.sce_status_string(s).decode()

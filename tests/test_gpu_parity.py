@@ -1,0 +1,267 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Error measures are normwise (entrywise relative errors are meaningless for
+modes whose rho is near zero):
+    e_rho = max_n |rho_gpu - rho_ref| / max_n |rho_ref|
+    e_F   = max_j |F_gpu,j - F_ref,j|_2 / max_j |F_ref,j|_2
+Tolerances: FP64 path <= 1e-12.  FP32 path: the phase tables are exact to
+FP32 rounding (u = 2^-24) and each product and running sum adds a few u, so
+the normwise error of either sum is O(10 u) ~ 1e-6 at these sizes; the tests
+use 1e-5, the accuracy asked of the force.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1508_07344_amd as sce
+    sce.load_library()
+    return sce
+
+
+def e_rho(r, ref):
+    return float(np.max(np.abs(r - ref)) / np.max(np.abs(ref)))
+
+
+def e_F(F, ref):
+    return float(np.max(np.linalg.norm(F - ref, axis=0)) / np.max(np.linalg.norm(ref, axis=0)))
+
+
+def _cases():
+    return [
+        ("one", workloads.random_particles(1, L=1.0, charge="positive").with_(n_max=3, a=0.05)),
+        ("two_body", workloads.two_body()),
+        ("tent", workloads.random_particles(333, L=2.3, charge="uniform").with_(n_max=5, shape="tent", a=0.2)),
+        ("delta", workloads.random_particles(1237, L=1.7, charge="alternating").with_(n_max=12, shape="delta", a=0.0)),
+        ("eps0", workloads.random_particles(517, L=1.0, charge="uniform").with_(n_max=4, a=0.03, eps0=0.25)),
+        ("plasma16", workloads.random_plasma(N=3001, n_max=16, a=0.02)),
+        ("plasma32", workloads.random_plasma(N=4099, n_max=32, a=0.01)),
+        ("n40", workloads.random_particles(700, L=1.0, charge="alternating").with_(n_max=40, a=0.01)),
+    ]
+
+
+@pytest.fixture(scope="module")
+def references():
+    _gpu()
+    out = {}
+    for name, p in _cases():
+        f = oracle.fields(p.positions(), p.q, p.L, p.n_max, p.shape, p.a, p.eps0)
+        out[name] = (p, f)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", [c[0] for c in _cases()])
+def test_deposit_and_force_match_oracle(references, name, prec):
+    sce = _gpu()
+    p, ref = references[name]
+    with sce.Context.from_particles(p, precision=prec) as c:
+        assert np.array_equal(c.sce_modes(), oracle.half_modes(p.n_max))
+        rho = c.sce_deposit()
+        psi = c.sce_psi()
+        F = c.sce_force()
+        d, st = c.sce_diagnostics()
+    er, ep, ef = e_rho(rho, ref.rho), e_rho(psi, ref.psi), e_F(F, ref.F) if p.N > 1 else 0.0
+    print(f"{name} {prec}: e_rho={er:.3e} e_psi={ep:.3e} e_F={ef:.3e}")
+    assert er <= TOL[prec] and ep <= TOL[prec]
+    if p.N > 1:
+        assert ef <= TOL[prec]
+    else:  # lone particle: no self-force, relative to the scale of one mode sum
+        k = oracle.wave_vectors(oracle.half_modes(p.n_max), p.L)
+        S = oracle.shape(p.shape, p.a, k)
+        scale = np.sum(2 * p.q[0] ** 2 * np.linalg.norm(k, axis=1) * S * S / np.sum(k * k, axis=1)) / (p.eps0 * p.L ** 3)
+        assert np.max(np.abs(F)) < TOL[prec] * scale
+    assert abs(d.field - ref.W) <= TOL[prec] * abs(ref.W)
+    assert abs(d.interaction - 2 * ref.W) <= (1e-12 if prec == "fp64" else 1e-5) * abs(ref.W)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_random_plasma_full_size_sampled(prec):
+    """N = 65536, n_max = 16: rho on sampled modes, F on sampled particles
+    (the oracle's F needs its own full rho, computed once)."""
+    sce = _gpu()
+    p = workloads.random_plasma()
+    modes = oracle.half_modes(p.n_max)
+    with sce.Context.from_particles(p, precision=prec) as c:
+        rho = c.sce_deposit()
+        F = c.sce_force()
+    rng = np.random.default_rng(11)
+    mi = np.sort(rng.choice(len(modes), 512, replace=False))
+    ref_rho_s = oracle.deposit(p.positions(), p.q, p.L, modes[mi], p.shape, p.a)
+    assert np.max(np.abs(rho[mi] - ref_rho_s)) <= TOL[prec] * np.max(np.abs(ref_rho_s))
+    ref_rho = oracle.deposit(p.positions(), p.q, p.L, modes, p.shape, p.a)
+    assert e_rho(rho, ref_rho) <= TOL[prec]
+    ref_psi = oracle.psi(ref_rho, p.L, modes, p.eps0, p.shape, p.a)
+    pj = np.sort(rng.choice(p.N, 256, replace=False))
+    sub = p.subset(pj)
+    Fref = oracle.force_from_psi(sub.positions(), sub.q, p.L, modes, ref_psi)
+    err = e_F(F[:, pj], Fref)
+    print(f"plasma65536 {prec}: e_rho={e_rho(rho, ref_rho):.3e} e_F(sample)={err:.3e}")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cold_lattice_full_size(prec):
+    """N = 1,048,576 lattice, n_max = 32: rho on sampled modes (including the
+    perturbed one) against the oracle; F through properties that hold at any
+    size: total force ~ 0 and sum_j q_j Phi_j = 2 W."""
+    sce = _gpu()
+    p = workloads.cold_lattice()
+    modes = oracle.half_modes(p.n_max)
+    with sce.Context.from_particles(p, precision=prec) as c:
+        rho = c.sce_deposit()
+        F = c.sce_force()
+        d, st = c.sce_diagnostics()
+    rng = np.random.default_rng(5)
+    k1 = int(np.nonzero((modes == [1, 0, 0]).all(axis=1))[0][0])
+    mi = np.unique(np.concatenate([[k1], rng.choice(len(modes), 47, replace=False)]))
+    ref = oracle.deposit(p.positions(), p.q, p.L, modes[mi], p.shape, p.a)
+    err = float(np.max(np.abs(rho[mi] - ref)) / np.max(np.abs(ref)))
+    print(f"lattice {prec}: e_rho(sample)={err:.3e} |rho_k1|={abs(ref[np.searchsorted(mi, k1)]):.4g}")
+    assert err <= TOL[prec]
+    Fs = np.sum(np.linalg.norm(F, axis=0))
+    assert np.max(np.abs(F.sum(axis=1))) <= (1e-11 if prec == "fp64" else 1e-5) * Fs
+    assert abs(d.interaction - 2 * d.field) <= (1e-12 if prec == "fp64" else 1e-5) * abs(d.field)
+
+
+def test_fp32_matches_fp64_gpu_at_full_size():
+    """Same inputs, FP32 vs FP64 GPU path, N = 1,048,576, n_max = 32."""
+    sce = _gpu()
+    p = workloads.cold_lattice()
+    out = {}
+    for prec in ("fp64", "fp32"):
+        with sce.Context.from_particles(p, precision=prec) as c:
+            out[prec] = (c.sce_deposit(), c.sce_force())
+    er = e_rho(out["fp32"][0], out["fp64"][0])
+    ef = e_F(out["fp32"][1], out["fp64"][1])
+    print(f"lattice fp32 vs fp64: e_rho={er:.3e} e_F={ef:.3e}")
+    assert er <= 1e-5 and ef <= 1e-5
+
+
+def test_device_tensors_in_and_out():
+    sce = _gpu()
+    import torch
+    p = workloads.random_plasma(N=2048, n_max=8, a=0.05)
+    ref = oracle.fields(p.positions(), p.q, p.L, p.n_max, p.shape, p.a)
+    with sce.Context.from_particles(p, device=True) as c:
+        rho_d = torch.zeros(2 * c.sce_mode_count(), dtype=torch.float64, device="cuda")
+        F_d = torch.zeros(3, p.N, dtype=torch.float64, device="cuda")
+        c.sce_deposit(rho_d)
+        c.sce_force(F_d)
+        c.sce_sync()
+        r = rho_d.cpu().numpy()
+        assert e_rho(r[0::2] + 1j * r[1::2], ref.rho) <= 1e-12
+        assert e_F(F_d.cpu().numpy(), ref.F) <= 1e-12
+
+
+# --------------------------------------------------------------------- steps
+@pytest.mark.parametrize("scheme,steps", [("kdk", 2000), ("dkd", 300)])
+def test_two_body_trajectory_matches_oracle(scheme, steps):
+    sce = _gpu()
+    p = workloads.two_body()
+    s = oracle.State.from_particles(p)
+    (oracle.step_kdk if scheme == "kdk" else oracle.step_dkd)(s, p.dt, steps)
+    with sce.Context.from_particles(p, scheme=scheme) as c:
+        c.sce_step(p.dt, steps)
+        x, v = c.sce_get_particles()
+        d, st = c.sce_diagnostics()
+    dx = np.max(np.abs((x - s.pos + 0.5) % 1.0 - 0.5))
+    dv = np.max(np.abs(v - s.vel))
+    print(f"two-body {scheme} {steps} steps: dx={dx:.3e} dv={dv:.3e}")
+    assert dx < 1e-9 and dv < 1e-9
+    e = oracle.energy(s)
+    assert abs(d.total - e["total"]) < 1e-10 * abs(e["total"])
+    assert np.max(np.abs(d.momentum)) <= 1e-12 * d.momentum_abs_sum
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_short_plasma_run_matches_oracle(prec):
+    sce = _gpu()
+    p = workloads.random_plasma(N=512, n_max=8, a=0.05, sigma_v=0.05)
+    s = oracle.State.from_particles(p)
+    oracle.step_kdk(s, 1e-3, 20)
+    with sce.Context.from_particles(p, precision=prec) as c:
+        c.sce_step(1e-3, 20)
+        x, v = c.sce_get_particles()
+    dx = np.max(np.abs((x - s.pos + 0.5) % 1.0 - 0.5))
+    tol = 1e-11 if prec == "fp64" else 1e-7
+    print(f"plasma512 {prec} 20 steps: dx={dx:.3e}")
+    assert dx < tol
+
+
+def test_momentum_conserved_fp64():
+    sce = _gpu()
+    p = workloads.random_plasma(N=65536, n_max=16)
+    with sce.Context.from_particles(p) as c:
+        d0, _ = c.sce_diagnostics()
+        c.sce_step(p.dt, 20)
+        d1, _ = c.sce_diagnostics()
+    rel = np.max(np.abs(d1.momentum - d0.momentum)) / d1.momentum_abs_sum
+    print(f"momentum error after 20 steps: {rel:.3e}")
+    assert rel <= 1e-12
+
+
+def test_bitwise_determinism_and_resume():
+    sce = _gpu()
+    p = workloads.random_plasma(N=5000, n_max=12, a=0.03)
+    with sce.Context.from_particles(p) as c:
+        r1 = c.sce_deposit()
+        r2 = c.sce_deposit()
+        assert np.array_equal(r1.view(np.float64), r2.view(np.float64))
+        c.sce_step(p.dt, 5)
+        blob = c.sce_get_state()
+        c.sce_step(p.dt, 5)
+        xa, va = c.sce_get_particles()
+    with sce.Context(p.L, p.n_max, p.shape, p.a) as c2:
+        c2.sce_set_state(blob)
+        c2.sce_step(p.dt, 5)
+        xb, vb = c2.sce_get_particles()
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+
+
+def test_cold_plasma_frequency_at_full_size():
+    """Whole loop at N = 1,048,576, n_max = 32, h = 5e-4, 50 steps: the k1 mode
+    oscillates at the paper's discrete frequency (2/h) asin(w_p h S(k1)/2)."""
+    sce = _gpu()
+    p = workloads.cold_lattice()
+    wp = math.sqrt(p.N / p.L ** 3)
+    S1 = math.exp(-0.5 * (2 * math.pi * p.a / p.L) ** 2)
+    w_ref = (2.0 / p.dt) * math.asin(wp * p.dt * S1 / 2.0)
+    k1 = _k1_index(p.n_max)
+    assert tuple(oracle.half_modes(p.n_max)[k1]) == (1, 0, 0)
+    series = []
+    with sce.Context.from_particles(p, precision="fp32") as c:
+        for _ in range(p.n_steps):
+            c.sce_step(p.dt, 1)
+            series.append(c.sce_deposit()[k1].real)
+    series = np.array(series)
+    t = p.dt * np.arange(1, len(series) + 1)
+    best = None
+    for w in np.linspace(0.9 * w_ref, 1.1 * w_ref, 2001):
+        A = np.stack([np.cos(w * t), np.sin(w * t), np.ones_like(t)], axis=1)
+        coef, *_ = np.linalg.lstsq(A, series, rcond=None)
+        r = np.sum((A @ coef - series) ** 2)
+        if best is None or r < best[0]:
+            best = (r, w)
+    print(f"omega={best[1]:.3f} reference={w_ref:.3f}")
+    assert abs(best[1] / w_ref - 1) < 2e-3
+
+
+def _k1_index(n):
+    """Canonical index of mode (1, 0, 0): after the n_x = 0 block (n + n(2n+1)
+    modes) and the n_y = -n..-1 rows of n_x = 1, at n_z = 0."""
+    return n + n * (2 * n + 1) + n * (2 * n + 1) + n
