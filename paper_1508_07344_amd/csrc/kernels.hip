@@ -123,6 +123,15 @@ k_deposit(const T *__restrict__ tab, const double *__restrict__ q, int64_t N, in
 #pragma unroll
     for (int k = 0; k < ZB; ++k) aP[k][0] = aP[k][1] = aQ[k][0] = aQ[k][1] = (T)0;
     T a0r = 0, a0i = 0;
+    // FP32 sums run over one LDS chunk (<= kc particles) and are then added
+    // into FP64 totals; a long FP32 running sum over coherent (lattice-like)
+    // terms would lose digits to its own growth.
+    constexpr bool kFlush = sizeof(T) < sizeof(double);
+    double dP[kFlush ? ZB : 1][2], dQ[kFlush ? ZB : 1][2], d0r = 0.0, d0i = 0.0;
+    if (kFlush) {
+#pragma unroll
+        for (int k = 0; k < (kFlush ? ZB : 1); ++k) dP[k][0] = dP[k][1] = dQ[k][0] = dQ[k][1] = 0.0;
+    }
 
     for (int64_t base = j0; base < j1; base += kc) {
         const int cnt = (int)((j1 - base) < kc ? (j1 - base) : kc);
@@ -165,6 +174,19 @@ k_deposit(const T *__restrict__ tab, const double *__restrict__ q, int64_t N, in
                     a0i += h.y;
                 }
             }
+            if (kFlush) {
+#pragma unroll
+                for (int k = 0; k < (kFlush ? ZB : 1); ++k) {
+                    dP[k][0] += (double)aP[k][0];
+                    dP[k][1] += (double)aP[k][1];
+                    dQ[k][0] += (double)aQ[k][0];
+                    dQ[k][1] += (double)aQ[k][1];
+                    aP[k][0] = aP[k][1] = aQ[k][0] = aQ[k][1] = (T)0;
+                }
+                d0r += (double)a0r;
+                d0i += (double)a0i;
+                a0r = a0i = (T)0;
+            }
         }
         __syncthreads();
     }
@@ -175,15 +197,16 @@ k_deposit(const T *__restrict__ tab, const double *__restrict__ q, int64_t N, in
         for (int k = 0; k < ZB; ++k) {
             const int nz = z0 + k;
             if (nz <= n) {
-                pb[(int64_t)(nz * 4 + 0) * Rpad] = (double)aP[k][0];
-                pb[(int64_t)(nz * 4 + 1) * Rpad] = (double)aP[k][1];
-                pb[(int64_t)(nz * 4 + 2) * Rpad] = (double)aQ[k][0];
-                pb[(int64_t)(nz * 4 + 3) * Rpad] = (double)aQ[k][1];
+                const int kk = kFlush ? k : 0;
+                pb[(int64_t)(nz * 4 + 0) * Rpad] = kFlush ? dP[kk][0] : (double)aP[k][0];
+                pb[(int64_t)(nz * 4 + 1) * Rpad] = kFlush ? dP[kk][1] : (double)aP[k][1];
+                pb[(int64_t)(nz * 4 + 2) * Rpad] = kFlush ? dQ[kk][0] : (double)aQ[k][0];
+                pb[(int64_t)(nz * 4 + 3) * Rpad] = kFlush ? dQ[kk][1] : (double)aQ[k][1];
             }
         }
         if (group == 0) {
-            pb[0] = (double)a0r;
-            pb[(int64_t)Rpad] = (double)a0i;
+            pb[0] = kFlush ? d0r : (double)a0r;
+            pb[(int64_t)Rpad] = kFlush ? d0i : (double)a0i;
             pb[(int64_t)2 * Rpad] = 0.0;
             pb[(int64_t)3 * Rpad] = 0.0;
         }
