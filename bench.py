@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=16384,
                     help="particles in the oracle's timed sample (all modes)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="only run a plain device-to-device copy of this many MiB (five times), "
+                         "the reference kernel for scaling the FETCH_SIZE/WRITE_SIZE counters")
     return ap.parse_args()
 
 
@@ -126,6 +129,15 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": 4 * n, "launches": 5}), flush=True)
+        return
     p = workloads.cold_lattice()
     main_r = time_path(sce, p, a.precision, a.steps, a.warmup)
     variants = {}

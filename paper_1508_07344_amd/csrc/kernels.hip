@@ -51,28 +51,36 @@ __device__ inline double frac_lin(int a, double ta, int b, double tb)
 __device__ inline void cis_turns(double u, double &c, double &s) { sincospi(2.0 * u, &s, &c); }
 
 // ------------------------------------------------------------------ phase table
+// exy[j][d][k] = cis(2 pi k t_d) for d = x, y and k = 0..n in FP64 (anchors of
+// the deposit's row recurrences); tz[j][k] = (cos, sin)(2 pi k t_z) in the
+// working precision for k = 0..n, zeros up to zslots.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_phase_table(const double *__restrict__ pos, int64_t N, int n, int zslots, double invL,
-              T *__restrict__ tab)
+              double2 *__restrict__ exy, T *__restrict__ tz)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    T *out = tab + j * (int64_t)(6 * zslots);
+    const int n1 = n + 1;
     for (int d = 0; d < 3; ++d) {
         const double t = frac(pos[d * N + j] * invL);
         double c1, s1;
         cis_turns(t, c1, s1);
         double c = 1.0, s = 0.0;
-        for (int k = 0; k < zslots; ++k) {
+        const int kend = d < 2 ? n1 : zslots;
+        for (int k = 0; k < kend; ++k) {
             if (k > n) {
                 c = 0.0;
                 s = 0.0;
             } else if (k > 0 && (k & 7) == 0) {
                 cis_turns(frac_mul(k, t), c, s);
             }
-            out[2 * (d * zslots + k)] = (T)c;
-            out[2 * (d * zslots + k) + 1] = (T)s;
+            if (d < 2) {
+                exy[(j * 2 + d) * n1 + k] = make_double2(c, s);
+            } else {
+                tz[(j * zslots + k) * 2] = (T)c;
+                tz[(j * zslots + k) * 2 + 1] = (T)s;
+            }
             const double cn = c * c1 - s * s1;
             s = s * c1 + c * s1;
             c = cn;
@@ -82,25 +90,102 @@ k_phase_table(const double *__restrict__ pos, int64_t N, int n, int zslots, doub
 
 template <typename T>
 hipError_t launch_phase_table(hipStream_t s, const double *pos, int64_t N, const Geom &g,
-                              double L, T *tab)
+                              double L, double2 *exy, T *tz)
 {
     const int64_t blocks = (N + 255) / 256;
     hipLaunchKernelGGL(k_phase_table<T>, dim3((unsigned)blocks), dim3(256), 0, s, pos, N, g.n,
-                       g.zslots, 1.0 / L, tab);
+                       g.zslots, 1.0 / L, exy, tz);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ deposit
 // Block = 4 waves.  A wave owns 64 rows (one per lane) and one group of ZB
-// n_z values; waves of a block share their rows' h values, staged per chunk of
-// kc particles in LDS.  The per-particle cos/sin of the wave's n_z group are
-// wave-uniform and read with scalar loads.  blockIdx.z selects the particle
-// split whose partial sums the block writes.
+// n_z values; waves of a block share their rows' h values, generated per chunk
+// of kc particles into LDS.  The per-particle cos/sin of the wave's n_z group
+// are wave-uniform: scalar loads, double-buffered so that the next particle's
+// values arrive while the current particle's FMAs issue.  blockIdx.z selects
+// the particle split whose partial sums the block writes.
+
+template <typename T, int ZB>
+__device__ __forceinline__ void load_cs(T (&c)[2 * ZB], const T *__restrict__ p)
+{
+#pragma unroll
+    for (int k = 0; k < 2 * ZB; ++k) c[k] = p[k];
+}
+
+template <typename T, int ZB, typename CT>
+__device__ __forceinline__ void fma_cs(const T (&c)[2 * ZB], CT h, T (&aP)[ZB][2], T (&aQ)[ZB][2])
+{
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+        aP[k][0] = fma(h.x, c[2 * k], aP[k][0]);
+        aP[k][1] = fma(h.y, c[2 * k], aP[k][1]);
+        aQ[k][0] = fma(h.x, c[2 * k + 1], aQ[k][0]);
+        aQ[k][1] = fma(h.y, c[2 * k + 1], aQ[k][1]);
+    }
+}
+
+// One LDS chunk for one lane: cnt particles, h from LDS (stride rows), the
+// z-table rows from zt (stride zs2).  G0: this wave also sums n_z = 0.
+// Software-pipelined: the loads of particle j+1 (LDS h and the scalar z row)
+// are issued before the FMAs of particle j, which use registers only; past
+// the end of the chunk h is zero (and the z row a valid duplicate), so the
+// extra step adds nothing.
+template <typename T, int ZB, bool G0, typename CT>
+__device__ __forceinline__ void dep_chunk(const CT *__restrict__ hrow, int rows, const T *__restrict__ zt,
+                                          int zs2, int cnt, T (&aP)[ZB][2], T (&aQ)[ZB][2],
+                                          T &a0r, T &a0i)
+{
+    if constexpr (sizeof(T) * ZB <= 32) {
+        T cA[2 * ZB], cB[2 * ZB];
+        CT hA, hB;
+        load_cs<T, ZB>(cA, zt);
+        hA = hrow[0];
+        for (int jj = 0; jj < cnt; jj += 2) {
+            const int j1 = jj + 1 < cnt ? jj + 1 : cnt - 1;
+            load_cs<T, ZB>(cB, zt + (int64_t)j1 * zs2);
+            hB = hrow[j1 * rows];
+            if (jj + 1 >= cnt) {
+                hB.x = (T)0;
+                hB.y = (T)0;
+            }
+            fma_cs<T, ZB>(cA, hA, aP, aQ);
+            if (G0) {
+                a0r += hA.x;
+                a0i += hA.y;
+            }
+            const int j2 = jj + 2 < cnt ? jj + 2 : cnt - 1;
+            load_cs<T, ZB>(cA, zt + (int64_t)j2 * zs2);
+            hA = hrow[j2 * rows];
+            fma_cs<T, ZB>(cB, hB, aP, aQ);
+            if (G0) {
+                a0r += hB.x;
+                a0i += hB.y;
+            }
+        }
+    } else {
+        // wide rows (FP64 x 8): one z row in scalar registers at a time
+        CT hA = hrow[0];
+        for (int jj = 0; jj < cnt; ++jj) {
+            T c[2 * ZB];
+            load_cs<T, ZB>(c, zt + (int64_t)jj * zs2);
+            const int j1 = jj + 1 < cnt ? jj + 1 : jj;
+            const CT hB = hrow[j1 * rows];
+            fma_cs<T, ZB>(c, hA, aP, aQ);
+            if (G0) {
+                a0r += hA.x;
+                a0i += hA.y;
+            }
+            hA = hB;
+        }
+    }
+}
+
 template <typename T, int ZB>
 __global__ void __launch_bounds__(256)
-k_deposit(const T *__restrict__ tab, const double *__restrict__ q, int64_t N, int n, int R,
-          int Rpad, int zslots, int groups, int waves_per_rs, int rows_per_wg, int kc,
-          int64_t per_split, double *__restrict__ part)
+k_deposit(const double2 *__restrict__ exy, const T *__restrict__ tz, const double *__restrict__ q,
+          int64_t N, int n, int R, int Rpad, int zslots, int groups, int waves_per_rs,
+          int rows_per_wg, int kc, int64_t per_split, double *__restrict__ part)
 {
     typedef typename C2<T>::t CT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -117,7 +202,13 @@ k_deposit(const T *__restrict__ tab, const double *__restrict__ q, int64_t N, in
     const int64_t j0 = (int64_t)blockIdx.z * per_split;
     const int64_t j1 = j0 + per_split < N ? j0 + per_split : N;
     const int z0 = 1 + group * ZB;
-    const int64_t pstride = 6 * (int64_t)zslots;
+    const int n1 = n + 1;
+    const int zs2 = 2 * zslots;
+    // h generation: each thread fills seg consecutive rows of one particle
+    const int seg = kc * rows_per_wg / 256;
+    const int segs_per_particle = rows_per_wg / seg;
+    const int g_jj = tid / segs_per_particle;
+    const int g_rl0 = (tid - g_jj * segs_per_particle) * seg;
 
     T aP[ZB][2], aQ[ZB][2];
 #pragma unroll
@@ -135,45 +226,66 @@ k_deposit(const T *__restrict__ tab, const double *__restrict__ q, int64_t N, in
 
     for (int64_t base = j0; base < j1; base += kc) {
         const int cnt = (int)((j1 - base) < kc ? (j1 - base) : kc);
-        for (int idx = tid; idx < kc * rows_per_wg; idx += 256) {
-            const int jj = idx / rows_per_wg;
-            const int rl = idx - jj * rows_per_wg;
-            const int r = blockIdx.x * rows_per_wg + rl;
-            CT h;
-            h.x = (T)0;
-            h.y = (T)0;
-            if (jj < cnt && r < R) {
+        {
+            // h(r) = q exp(-i(nx tx + ny ty)) for seg rows: anchor from the FP64
+            // axis tables, then steps of exp(-i ty) along n_y (FP64).
+            int r = blockIdx.x * rows_per_wg + g_rl0;
+            CT *dst = hs + g_jj * rows_per_wg + g_rl0;
+            if (g_jj < cnt) {
+                const int64_t j = base + g_jj;
+                const double2 *ex = exy + j * 2 * n1;
+                const double2 *ey = ex + n1;
+                const double qq = q[j];
+                const double2 e1 = ey[1];
                 int nx, ny;
-                row_nxny(r, n, nx, ny);
-                const T *tj = tab + (base + jj) * pstride;
-                const T cx = tj[2 * nx], sx = -tj[2 * nx + 1];
-                const int ay = ny < 0 ? -ny : ny;
-                const T cy = tj[2 * (zslots + ay)];
-                const T sy = ny < 0 ? tj[2 * (zslots + ay) + 1] : -tj[2 * (zslots + ay) + 1];
-                const T qq = (T)q[base + jj];
-                h.x = qq * (cx * cy - sx * sy);
-                h.y = qq * (cx * sy + sx * cy);
+                row_nxny(r < R ? r : R - 1, n, nx, ny);
+                double hc = 0.0, hs_ = 0.0;
+                bool fresh = true;
+                for (int s = 0; s < seg; ++s, ++r) {
+                    if (r >= R) {
+                        dst[s].x = (T)0;
+                        dst[s].y = (T)0;
+                        continue;
+                    }
+                    if (fresh) {
+                        // exp(-i nx tx) * exp(-i ny ty)
+                        const double2 a = ex[nx];
+                        const int ay = ny < 0 ? -ny : ny;
+                        const double2 b = ey[ay];
+                        const double bs = ny < 0 ? b.y : -b.y;
+                        const double as = -a.y;
+                        hc = qq * (a.x * b.x - as * bs);
+                        hs_ = qq * (a.x * bs + as * b.x);
+                        fresh = false;
+                    }
+                    dst[s].x = (T)hc;
+                    dst[s].y = (T)hs_;
+                    if (ny < n) {
+                        ++ny;
+                        const double t = hc * e1.x + hs_ * e1.y;
+                        hs_ = hs_ * e1.x - hc * e1.y;
+                        hc = t;
+                    } else {
+                        ++nx;
+                        ny = -n;
+                        fresh = true;
+                    }
+                }
+            } else {
+                for (int s = 0; s < seg; ++s) {
+                    dst[s].x = (T)0;
+                    dst[s].y = (T)0;
+                }
             }
-            hs[idx] = h;
         }
         __syncthreads();
         if (active) {
-            for (int jj = 0; jj < cnt; ++jj) {
-                const CT h = hs[jj * rows_per_wg + row_local];
-                const T *cs = tab + (base + jj) * pstride + 2 * (2 * zslots + z0);
-#pragma unroll
-                for (int k = 0; k < ZB; ++k) {
-                    const T c = cs[2 * k], s = cs[2 * k + 1];
-                    aP[k][0] = fma(h.x, c, aP[k][0]);
-                    aP[k][1] = fma(h.y, c, aP[k][1]);
-                    aQ[k][0] = fma(h.x, s, aQ[k][0]);
-                    aQ[k][1] = fma(h.y, s, aQ[k][1]);
-                }
-                if (group == 0) {
-                    a0r += h.x;
-                    a0i += h.y;
-                }
-            }
+            const CT *hrow = hs + row_local;
+            const T *zt = tz + base * zs2 + 2 * z0;
+            if (group == 0)
+                dep_chunk<T, ZB, true>(hrow, rows_per_wg, zt, zs2, cnt, aP, aQ, a0r, a0i);
+            else
+                dep_chunk<T, ZB, false>(hrow, rows_per_wg, zt, zs2, cnt, aP, aQ, a0r, a0i);
             if (kFlush) {
 #pragma unroll
                 for (int k = 0; k < (kFlush ? ZB : 1); ++k) {
@@ -192,7 +304,7 @@ k_deposit(const T *__restrict__ tab, const double *__restrict__ q, int64_t N, in
     }
 
     if (active && row < R) {
-        double *pb = part + (int64_t)blockIdx.z * (int64_t)(n + 1) * 4 * Rpad + row;
+        double *pb = part + (int64_t)blockIdx.z * (int64_t)n1 * 4 * Rpad + row;
 #pragma unroll
         for (int k = 0; k < ZB; ++k) {
             const int nz = z0 + k;
@@ -241,18 +353,18 @@ DepositPlan plan_deposit(const Geom &g, int64_t N, int elem_bytes)
 }
 
 template <typename T>
-hipError_t launch_deposit(hipStream_t s, const T *tab, const double *q, int64_t N, const Geom &g,
-                          const DepositPlan &pl, double *part)
+hipError_t launch_deposit(hipStream_t s, const double2 *exy, const T *tz, const double *q, int64_t N,
+                          const Geom &g, const DepositPlan &pl, double *part)
 {
     typedef typename C2<T>::t CT;
     const size_t shmem = (size_t)pl.kc * pl.rows_per_wg * sizeof(CT);
     dim3 grid((unsigned)pl.row_blocks, (unsigned)pl.grid_y, (unsigned)pl.splits);
     if (pl.zb == 4)
-        hipLaunchKernelGGL((k_deposit<T, 4>), grid, dim3(256), shmem, s, tab, q, N, g.n, g.R,
+        hipLaunchKernelGGL((k_deposit<T, 4>), grid, dim3(256), shmem, s, exy, tz, q, N, g.n, g.R,
                            g.Rpad, g.zslots, pl.groups, pl.waves_per_rs, pl.rows_per_wg, pl.kc,
                            pl.per_split, part);
     else
-        hipLaunchKernelGGL((k_deposit<T, 8>), grid, dim3(256), shmem, s, tab, q, N, g.n, g.R,
+        hipLaunchKernelGGL((k_deposit<T, 8>), grid, dim3(256), shmem, s, exy, tz, q, N, g.n, g.R,
                            g.Rpad, g.zslots, pl.groups, pl.waves_per_rs, pl.rows_per_wg, pl.kc,
                            pl.per_split, part);
     return hipGetLastError();
@@ -474,7 +586,7 @@ hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const
                         int64_t N, double kick, double *F, double *phi)
 {
     const int64_t blocks = (N + 255) / 256;
-    const int nzc = g.nzp <= 8 ? 8 : (g.nzp <= 16 ? 16 : 32);
+    const int nzc = force_chunk(g.n, (int)sizeof(T));
     if (nzc == 8)
         hipLaunchKernelGGL((k_force<T, 8>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
                            vel, ftab, psi0, g.n, g.nzp, 1.0 / L, N, kick, F, phi);
@@ -597,10 +709,10 @@ hipError_t launch_diag(hipStream_t s, const double *vel, const double *q, const 
 }
 
 // explicit instantiations
-template hipError_t launch_phase_table<float>(hipStream_t, const double *, int64_t, const Geom &, double, float *);
-template hipError_t launch_phase_table<double>(hipStream_t, const double *, int64_t, const Geom &, double, double *);
-template hipError_t launch_deposit<float>(hipStream_t, const float *, const double *, int64_t, const Geom &, const DepositPlan &, double *);
-template hipError_t launch_deposit<double>(hipStream_t, const double *, const double *, int64_t, const Geom &, const DepositPlan &, double *);
+template hipError_t launch_phase_table<float>(hipStream_t, const double *, int64_t, const Geom &, double, double2 *, float *);
+template hipError_t launch_phase_table<double>(hipStream_t, const double *, int64_t, const Geom &, double, double2 *, double *);
+template hipError_t launch_deposit<float>(hipStream_t, const double2 *, const float *, const double *, int64_t, const Geom &, const DepositPlan &, double *);
+template hipError_t launch_deposit<double>(hipStream_t, const double2 *, const double *, const double *, int64_t, const Geom &, const DepositPlan &, double *);
 template hipError_t launch_reduce_solve<float>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, float *, float *, double *, int *);
 template hipError_t launch_reduce_solve<double>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, double *, double *, double *, int *);
 template hipError_t launch_force<float>(hipStream_t, const double *, const double *, const double *, double *, const float *, const float *, const Geom &, double, int64_t, double, double *, double *);

@@ -42,8 +42,10 @@ struct sce_ctx_s {
     int64_t N = 0, cap = 0;
     double *pos = nullptr, *vel = nullptr, *q = nullptr, *m = nullptr, *F = nullptr,
            *phi = nullptr;
-    void *tab = nullptr;
+    void *tab = nullptr;        // z phase table, working precision
     size_t tab_bytes = 0;
+    void *tabxy = nullptr;      // x/y phase tables, FP64
+    size_t tabxy_bytes = 0;
     double *part = nullptr;
     size_t part_bytes = 0;
     double *Stab = nullptr, *Gtab = nullptr, *Ktab = nullptr;
@@ -92,8 +94,6 @@ sce_status hipfail(sce_ctx c, hipError_t e, const char *what)
         if (_e != hipSuccess) return hipfail(c, _e, #expr); \
     } while (0)
 
-int force_chunk(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : 32); }
-
 Geom make_geom(int n)
 {
     Geom g;
@@ -104,11 +104,11 @@ Geom make_geom(int n)
     g.Rpad = (g.R + 63) / 64 * 64;
     g.P = (int64_t)g.R * g.M;
     g.H = g.P - (n + 1);
-    const int c = force_chunk(n);
+    // force table slots: a multiple of the widest register chunk (FP32's)
+    const int c = sce::force_chunk(n, 4);
     g.nzp = (n + c - 1) / c * c;
-    const int zb = n <= 4 ? 4 : 8;
-    const int groups = (n + zb - 1) / zb;
-    g.zslots = 1 + groups * zb;
+    // covers the n_z groups of either deposit tiling (4 or 8 per group)
+    g.zslots = 1 + (n + 7) / 8 * 8;
     return g;
 }
 
@@ -244,7 +244,9 @@ sce_status run_deposit(sce_ctx c)
 {
     const Geom &g = c->g;
     const sce::DepositPlan pl = sce::plan_deposit(g, c->N, (int)sizeof(T));
-    sce_status st = ensure_bytes(c, c->tab, c->tab_bytes, (size_t)c->N * 6 * g.zslots * sizeof(T));
+    sce_status st = ensure_bytes(c, c->tab, c->tab_bytes, (size_t)c->N * 2 * g.zslots * sizeof(T));
+    if (st) return st;
+    st = ensure_bytes(c, c->tabxy, c->tabxy_bytes, (size_t)c->N * 2 * g.n1 * sizeof(double2));
     if (st) return st;
     size_t pb = c->part_bytes;
     void *pp = c->part;
@@ -252,14 +254,16 @@ sce_status run_deposit(sce_ctx c)
     c->part = (double *)pp;
     c->part_bytes = pb;
     if (st) return st;
-    HIPCHK(c, sce::launch_phase_table<T>(c->stream, c->pos, c->N, g, c->L, (T *)c->tab));
+    HIPCHK(c, sce::launch_phase_table<T>(c->stream, c->pos, c->N, g, c->L, (double2 *)c->tabxy,
+                                         (T *)c->tab));
     EventPair ep{nullptr, nullptr};
     if (c->timing) {
         ep.a = take_event(c);
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
-    HIPCHK(c, sce::launch_deposit<T>(c->stream, (const T *)c->tab, c->q, c->N, g, pl, c->part));
+    HIPCHK(c, sce::launch_deposit<T>(c->stream, (const double2 *)c->tabxy, (const T *)c->tab, c->q,
+                                     c->N, g, pl, c->part));
     if (c->timing && ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_dep.push_back(ep);
@@ -711,6 +715,7 @@ void sce_destroy(sce_ctx c)
     free_devp(c->F);
     free_devp(c->phi);
     free_dev(c->tab);
+    free_dev(c->tabxy);
     free_devp(c->part);
     free_devp(c->Stab);
     free_devp(c->Gtab);

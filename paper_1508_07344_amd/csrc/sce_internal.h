@@ -36,6 +36,14 @@ __host__ __device__ inline void row_nxny(int r, int n, int &nx, int &ny)
     ny = rr % M - n;
 }
 
+// n_z values per register chunk of the force kernel: 8, 16 or 32; FP64 caps
+// at 16 (cos/sin of 16 n_z in 64 VGPRs keeps three waves per SIMD).
+inline int force_chunk(int n, int elem_bytes)
+{
+    const int c = n <= 8 ? 8 : (n <= 16 ? 16 : 32);
+    return elem_bytes == 8 && c > 16 ? 16 : c;
+}
+
 __host__ __device__ inline bool in_half(int nx, int ny, int nz)
 {
     return nx > 0 || (nx == 0 && (ny > 0 || (ny == 0 && nz > 0)));
@@ -44,11 +52,12 @@ __host__ __device__ inline bool in_half(int nx, int ny, int nz)
 // Kernel launchers (kernels.hip).  All return hipError_t of the launch.
 // Precision-templated launchers take T = float or double.
 
-// Per-particle phase table tab[j][3][zslots] of complex T: (cos, sin)(k theta_d)
-// for k = 0..n (k <= n) and zeros up to zslots, theta_d = 2 pi x_d / L.
+// Per-particle phase tables, theta_d = 2 pi x_d / L:
+//   exy[j][d][k] = (cos, sin)(k theta_d), d = x, y, k = 0..n, FP64;
+//   tz[j][k]     = (cos, sin)(k theta_z), k = 0..n, zeros up to zslots, type T.
 template <typename T>
 hipError_t launch_phase_table(hipStream_t s, const double *pos, int64_t N, const Geom &g,
-                              double L, T *tab);
+                              double L, double2 *exy, T *tz);
 
 // Deposit partial sums for one particle split per blockIdx.z.  part layout
 // [split][n_z in 0..n][4][Rpad] doubles: (P_re, P_im, Q_re, Q_im) with
@@ -66,8 +75,8 @@ struct DepositPlan {
 };
 DepositPlan plan_deposit(const Geom &g, int64_t N, int elem_bytes);
 template <typename T>
-hipError_t launch_deposit(hipStream_t s, const T *tab, const double *q, int64_t N, const Geom &g,
-                          const DepositPlan &pl, double *part);
+hipError_t launch_deposit(hipStream_t s, const double2 *exy, const T *tz, const double *q, int64_t N,
+                          const Geom &g, const DepositPlan &pl, double *part);
 
 // Sum the partials over splits in fixed order, form rho and psi on the padded
 // layout, the force table and the per-block (W, max|rho|) partials.
