@@ -28,9 +28,11 @@ sys.path.insert(0, ROOT)
 METRIC = ("particle×mode pairs/s per step (FP64 vs split-precision); "
           "serve p50/p99 step latency")
 
-# Published MI355X vector peaks (256 CUs, 2.4 GHz).  The FP32 figure counts
-# packed-FP32 issue; the FP64 figure is one FMA per lane per clock.
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# Published MI355X peaks (256 CUs, 2.4 GHz): vector FP64 and FP32 (the FP32
+# figure counts packed-FP32 issue), dense FP16 matrix cores for the split path.
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_f16": 2500.0}
+BOUND = {"fp64": "alu", "fp32": "alu", "split_f16": "mfma"}
+DTYPE = {"fp64": "f64", "fp32": "f32", "split_f16": "f16"}
 # Algorithmic flops per particle x mode pair, counted as complex multiply-adds
 # of the separable sums: deposit 1 complex MAC (8), force 2 complex MACs (16).
 FLOPS_PER_PAIR = {"deposit": 8, "force": 16}
@@ -41,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "split_f16"])
     ap.add_argument("--also", default="fp64", help="comma list of extra precisions to time")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=16384,
@@ -93,10 +95,12 @@ def roofline(r, N):
     achieved = FLOPS_PER_PAIR["force"] * pairs / t / 1e12
     peak = PEAK_TFLOPS[r["precision"]]
     dep = FLOPS_PER_PAIR["deposit"] * pairs / (r["deposit_ms_avg"] * 1e-3) / 1e12
-    return {"bound": "alu", "kernel": "k_force", "achieved": round(achieved, 3), "peak": peak,
+    mf = r["precision"] == "split_f16"
+    return {"bound": BOUND[r["precision"]], "kernel": "k_force_mfma" if mf else "k_force",
+            "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "deposit_kernel": {"kernel": "k_deposit", "achieved": round(dep, 3),
-                               "frac": round(dep / peak, 4)}}
+            "deposit_kernel": {"kernel": "k_deposit_mfma" if mf else "k_deposit",
+                               "achieved": round(dep, 3), "frac": round(dep / peak, 4)}}
 
 
 def cpu_baseline(p, sample):
@@ -155,7 +159,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32"}[a.precision],
+        "dtype": DTYPE[a.precision],
         "data": "synthetic",
         "config": {"workload": "cold_lattice_128x128x64_n32", "N": p.N, "n_max": p.n_max,
                    "modes_half": main_r["modes_half"], "shape": "gaussian", "a": p.a,

@@ -1,0 +1,655 @@
+// Split-precision matrix-core kernels (gfx950, v_mfma_f32_16x16x32_f16) for
+// the two particle x mode sums.
+//
+// With separable phases (modes spaced 2 pi / L, Section 8) both sums are dense
+// contractions:
+//   deposit  C[c, r] = sum_j CS[c, j] H[j, r]         (K = particles)
+//            CS[c, j] = cos(c tz_j) for c = 0..n, sin((c-n) tz_j) for c = n+1..2n
+//            H[j, r]  = q_j exp(-i (nx tx_j + ny ty_j))   (real and imaginary parts
+//                       as two GEMMs), so C gives P (cos rows) and Q (sin rows).
+//   force    U[(r, e), j] = sum_k W[(r, e), k] CS'[k, j]   (K = cos and sin of n_z = 1..)
+//            e = (Re U0, Im U0, Re U1, Im U1) of the row's n_z sums, then
+//            F_j += (nx Im(g U0), ny Im(g U0), Im(g U1)), g = exp(i (nx tx + ny ty)).
+// Every FP32 operand x is carried as two FP16 values hi = fp16(x),
+// lo = fp16(x - hi); a product uses hi*hi + hi*lo + lo*hi (the lo*lo term,
+// ~2^-22 relative, is dropped), accumulated in FP32 by the matrix core.
+// Operands are scaled to magnitude <= 1 first (charges by 1/max|q|, the
+// force table by 1/max|entry|) so FP16's range is never exceeded.
+//
+// Fragment layout of v_mfma_f32_16x16x32_f16 (lane l, element i):
+//   A[m][k]: m = l % 16, k = 8 (l / 16) + i     (8 halves)
+//   B[k][n]: k = 8 (l / 16) + i, n = l % 16     (8 halves)
+//   D[m][n]: m = 4 (l / 16) + i, n = l % 16     (4 floats)
+
+#include "sce_internal.h"
+#include "sce_device.h"
+
+namespace sce {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void split_f16(float x, _Float16 &hi, _Float16 &lo)
+{
+    hi = (_Float16)x;
+    lo = (_Float16)(x - (float)hi);
+}
+
+__device__ inline f32x4 mfma16(half8 a, half8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// acc += (ah + al)(bh + bl) without the al*bl term
+__device__ inline f32x4 mfma_split(half8 ah, half8 al, half8 bh, half8 bl, f32x4 acc)
+{
+    acc = mfma16(al, bh, acc);
+    acc = mfma16(ah, bl, acc);
+    return mfma16(ah, bh, acc);
+}
+
+// Pseudo-random bijection of [0, N): a 4-round Feistel network on 2h bits
+// (2^(2h) >= N) with cycle-walking back into [0, N).  The deposit visits the
+// particles of a split in this order so that each split is an unstructured
+// sample of the particles: its FP32 sums then grow like random walks for every
+// mode, whatever the input order (an affine order i*A mod N is a rank-1
+// lattice and stays coherent for some wave vectors).
+__device__ inline uint32_t feistel_perm(uint32_t i, uint32_t N, int h)
+{
+    const uint32_t mask = h >= 16 ? 0xFFFFu : ((1u << h) - 1u);
+    uint32_t x = i;
+    do {
+        uint32_t L = x >> h, R = x & mask;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            uint32_t f = R * 0x9E3779B1u + 0x7F4A7C15u * (uint32_t)(r + 1);
+            f ^= f >> 15;
+            f *= 0x85EBCA6Bu;
+            f ^= f >> 13;
+            const uint32_t nl = R;
+            R = (L ^ f) & mask;
+            L = nl;
+        }
+        x = (L << h) | R;
+    } while (x >= N);
+    return x;
+}
+
+// ------------------------------------------------------------------ deposit
+// Block = 8 waves = 256 rows (two 16-row N tiles per wave), all CS rows
+// (MT tiles of 16).  blockIdx.y = particle split; the split's particles are
+// visited in the pseudo-random order of feistel_perm.  Per chunk of 32 particles:
+// the block builds per-particle tables in LDS (a = q cis(-nx tx) / qscale,
+// b = cis(-k ty), CS hi/lo), then every lane forms its own H fragment.
+constexpr int kDepRowsPerBlock = 256;
+constexpr int kDepChunk = 32;
+// Both deposit operands are multiplied by 7/8 before the split (and the
+// result by 64/49 in FP64).  Unscaled, cos(n_z theta) and h crowd just below
+// 1.0 for particles near the origin, where round-to-nearest FP16 gives hi = 1
+// and a negative lo in both operands: the dropped lo*lo term then has a
+// consistent sign and acts like a spurious charge at the origin.  At 7/8 no
+// operand sits at an FP16 exponent boundary and the lo parts are unbiased.
+constexpr float kDepOpScale = 0.875f;
+// The matrix core rounds its FP32 accumulation per group of products and, when
+// the running sum is much larger than each increment, slightly toward -inf.
+// Over thousands of chunks that directional bias is identical in every
+// accumulator and would act like a spurious charge at the origin.  The running
+// sum therefore changes sign every chunk (accumulator and CS operand negated
+// together), so the bias alternates direction and cancels.
+
+template <int MT>
+__global__ void __launch_bounds__(512)
+k_deposit_mfma(const double *__restrict__ pos /* turns */, const double *__restrict__ q, int64_t N, int n,
+               int R, int Rpad, int64_t perm, int64_t per_split, double qinv, double qscale,
+               double *__restrict__ part)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n1 = n + 1;
+    const int CSR = MT * 16;  // CS rows incl. padding
+    _Float16 *cs_hi = reinterpret_cast<_Float16 *>(smem);            // [CSR][32]
+    _Float16 *cs_lo = cs_hi + CSR * kDepChunk;                        // [CSR][32]
+    float2 *ta = reinterpret_cast<float2 *>(cs_lo + CSR * kDepChunk);  // [32][n1]
+    float2 *tb = ta + kDepChunk * n1;                                 // [32][n1]
+    double2 *c1 = reinterpret_cast<double2 *>(tb + kDepChunk * n1);    // [32][3] cis(t_d)
+    double *tq = reinterpret_cast<double *>(c1 + kDepChunk * 3);      // [32] scaled charges
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int g = lane >> 4;   // lane group: particles 8g..8g+7 of a chunk
+    const int ln = lane & 15;  // row within an N tile
+    const int64_t j0 = (int64_t)blockIdx.y * per_split;
+    const int64_t j1 = j0 + per_split < N ? j0 + per_split : N;
+
+    // zero CS padding rows once (never written afterwards)
+    for (int idx = tid; idx < (CSR - (2 * n + 1)) * kDepChunk; idx += 512) {
+        cs_hi[(2 * n + 1) * kDepChunk + idx] = (_Float16)0.0f;
+        cs_lo[(2 * n + 1) * kDepChunk + idx] = (_Float16)0.0f;
+    }
+
+    // this lane's two rows
+    int rnx[2], rny[2];
+    bool rok[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int r = blockIdx.x * kDepRowsPerBlock + wave * 32 + nt * 16 + ln;
+        rok[nt] = r < R;
+        row_nxny(r < R ? r : R - 1, n, rnx[nt], rny[nt]);
+    }
+
+    f32x4 acc[MT][2][2];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt][0] = acc[mt][nt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int nb = (n1 + 7) / 8;  // blocks of 8 powers per axis
+
+    for (int64_t base = j0; base < j1; base += kDepChunk) {
+        const int cnt = (int)((j1 - base) < kDepChunk ? (j1 - base) : kDepChunk);
+        const bool odd = (((base - j0) / kDepChunk) & 1) != 0;
+        const float csg = odd ? -kDepOpScale : kDepOpScale;
+        __syncthreads();  // previous chunk's tables are no longer read
+        // 1. fundamental phases cis(2 pi t_d) and scaled charges
+        if (tid < 3 * kDepChunk) {
+            const int p = tid / 3, d = tid - 3 * (tid / 3);
+            double cc = 1.0, ss = 0.0;
+            if (p < cnt) {
+                const int64_t jp = feistel_perm((uint32_t)(base + p), (uint32_t)N, (int)perm);
+                cis_turns(pos[d * N + jp], cc, ss);  // positions in turns
+                if (d == 0) tq[p] = q[jp] * qinv * (double)kDepOpScale;
+            } else if (d == 0) {
+                tq[p] = 0.0;
+            }
+            c1[p * 3 + d] = make_double2(cc, ss);
+        }
+        __syncthreads();
+        // 2. tables: task = (particle, axis, block of 8 powers)
+        for (int task = tid; task < kDepChunk * 3 * nb; task += 512) {
+            const int p = task / (3 * nb);
+            const int rem = task - p * 3 * nb;
+            const int d = rem / nb, blk = rem - d * nb;
+            const double2 e = c1[p * 3 + d];
+            // anchor cis(8 blk t) by repeated squaring of cis(t)
+            double ac = 1.0, as = 0.0;
+            {
+                double pc = e.x, ps = e.y;
+                int k = 8 * blk;
+                while (k) {
+                    if (k & 1) {
+                        const double t = ac * pc - as * ps;
+                        as = ac * ps + as * pc;
+                        ac = t;
+                    }
+                    const double t = pc * pc - ps * ps;
+                    ps = 2.0 * pc * ps;
+                    pc = t;
+                    k >>= 1;
+                }
+            }
+            const double qq = tq[p];
+            for (int kk = 0; kk < 8; ++kk) {
+                const int k = 8 * blk + kk;
+                if (k > n) break;
+                if (d == 0) {
+                    ta[p * n1 + k] = make_float2((float)(qq * ac), (float)(-qq * as));
+                } else if (d == 1) {
+                    tb[p * n1 + k] = make_float2((float)ac, (float)(-as));
+                } else {
+                    _Float16 h, l;
+                    split_f16((float)(csg * ac), h, l);
+                    cs_hi[k * kDepChunk + p] = h;
+                    cs_lo[k * kDepChunk + p] = l;
+                    if (k > 0) {
+                        split_f16((float)(csg * as), h, l);
+                        cs_hi[(n + k) * kDepChunk + p] = h;
+                        cs_lo[(n + k) * kDepChunk + p] = l;
+                    }
+                }
+                const double t = ac * e.x - as * e.y;
+                as = ac * e.y + as * e.x;
+                ac = t;
+            }
+        }
+        __syncthreads();
+        // 3. H fragments for this lane's two rows (particles 8g..8g+7)
+        half8 bre_h[2], bre_l[2], bim_h[2], bim_l[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int ay = rny[nt] < 0 ? -rny[nt] : rny[nt];
+            const float sgn = rny[nt] < 0 ? -1.0f : 1.0f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int p = 8 * g + i;
+                const float2 a = ta[p * n1 + rnx[nt]];
+                float2 b = tb[p * n1 + ay];
+                b.y *= sgn;
+                float hr = a.x * b.x - a.y * b.y;
+                float hi = a.x * b.y + a.y * b.x;
+                if (!rok[nt]) hr = hi = 0.0f;
+                _Float16 x0, x1;
+                split_f16(hr, x0, x1);
+                bre_h[nt][i] = x0;
+                bre_l[nt][i] = x1;
+                split_f16(hi, x0, x1);
+                bim_h[nt][i] = x0;
+                bim_l[nt][i] = x1;
+            }
+        }
+        // 4. matrix-core products over the chunk, running sum sign-alternated
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                acc[mt][nt][0] = -acc[mt][nt][0];
+                acc[mt][nt][1] = -acc[mt][nt][1];
+            }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const half8 ah = *reinterpret_cast<const half8 *>(&cs_hi[(mt * 16 + ln) * kDepChunk + 8 * g]);
+            const half8 al = *reinterpret_cast<const half8 *>(&cs_lo[(mt * 16 + ln) * kDepChunk + 8 * g]);
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                acc[mt][nt][0] = mfma_split(ah, al, bre_h[nt], bre_l[nt], acc[mt][nt][0]);
+                acc[mt][nt][1] = mfma_split(ah, al, bim_h[nt], bim_l[nt], acc[mt][nt][1]);
+            }
+        }
+    }
+
+    // after chunk c (0-based) the accumulators hold (-1)^c times the sum
+    const int64_t nchunks = (j1 - j0 + kDepChunk - 1) / kDepChunk;
+    const double fsign = (nchunks & 1) ? 1.0 : -1.0;
+    qscale *= fsign;
+    // partial sums of this split: D[m][r], m = CS row, r = row (lane's ln)
+    double *pb = part + (int64_t)blockIdx.y * (int64_t)n1 * 4 * Rpad;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const int r = blockIdx.x * kDepRowsPerBlock + wave * 32 + nt * 16 + ln;
+        if (!rok[nt]) continue;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = mt * 16 + 4 * g + i;
+                int nz, slot;
+                if (m <= n) {
+                    nz = m;
+                    slot = 0;
+                } else if (m <= 2 * n) {
+                    nz = m - n;
+                    slot = 2;
+                } else {
+                    continue;
+                }
+                pb[((int64_t)nz * 4 + slot) * Rpad + r] = qscale * (double)acc[mt][nt][0][i];
+                pb[((int64_t)nz * 4 + slot + 1) * Rpad + r] = qscale * (double)acc[mt][nt][1][i];
+                if (m == 0) {
+                    pb[((int64_t)0 * 4 + 2) * Rpad + r] = 0.0;
+                    pb[((int64_t)0 * 4 + 3) * Rpad + r] = 0.0;
+                }
+            }
+        }
+    }
+}
+
+int mfma_cs_tiles(int n) { return (2 * n + 1 + 15) / 16; }
+
+size_t deposit_mfma_lds(int n)
+{
+    const int n1 = n + 1;
+    return (size_t)mfma_cs_tiles(n) * 16 * kDepChunk * 2 * sizeof(_Float16) +
+           (size_t)2 * kDepChunk * n1 * sizeof(float2) + (size_t)kDepChunk * 3 * sizeof(double2) +
+           (size_t)kDepChunk * sizeof(double);
+}
+
+MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
+{
+    MfmaDepositPlan p;
+    p.row_blocks = (g.R + kDepRowsPerBlock - 1) / kDepRowsPerBlock;
+    int64_t splits = (1024 + p.row_blocks - 1) / p.row_blocks;
+    const int64_t max_splits = N / 512 > 1 ? N / 512 : 1;
+    if (splits > max_splits) splits = max_splits;
+    if (splits < 1) splits = 1;
+    int64_t per = (N + splits - 1) / splits;
+    per = (per + kDepChunk - 1) / kDepChunk * kDepChunk;
+    p.per_split = per;
+    p.splits = (int)((N + per - 1) / per);
+    // Feistel half width h: 2^(2h) >= N
+    int h = 0;
+    while (h < 16 && ((int64_t)1 << (2 * h)) < N) ++h;
+    p.perm = h;
+    return p;
+}
+
+template <int MT>
+static void launch_dep_mt(hipStream_t s, const double *pos, const double *q, int64_t N,
+                          const Geom &g, const MfmaDepositPlan &pl, double L, double qscale,
+                          double *part)
+{
+    (void)L;
+    const double unscale = qscale / ((double)kDepOpScale * (double)kDepOpScale);
+    hipLaunchKernelGGL(k_deposit_mfma<MT>, dim3(pl.row_blocks, pl.splits), dim3(512),
+                       deposit_mfma_lds(g.n), s, pos, q, N, g.n, g.R, g.Rpad, pl.perm,
+                       pl.per_split, 1.0 / qscale, unscale, part);
+}
+
+hipError_t launch_deposit_mfma(hipStream_t s, const double *pos_turns, const double *q, int64_t N,
+                               const Geom &g, const MfmaDepositPlan &pl, double qscale,
+                               double *part)
+{
+    switch (mfma_cs_tiles(g.n)) {
+    case 1: launch_dep_mt<1>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    case 2: launch_dep_mt<2>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    case 3: launch_dep_mt<3>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    case 4: launch_dep_mt<4>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    case 5: launch_dep_mt<5>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    case 6: launch_dep_mt<6>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    case 7: launch_dep_mt<7>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    case 8: launch_dep_mt<8>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    default: launch_dep_mt<9>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    }
+    return hipGetLastError();
+}
+
+// positions in turns: t = frac(x / L), [3][N]
+__global__ void __launch_bounds__(256)
+k_turns(const double *__restrict__ pos, int64_t n3, double invL, double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n3) out[i] = frac(pos[i] * invL);
+}
+
+hipError_t launch_turns(hipStream_t s, const double *pos, int64_t N, double L, double *out)
+{
+    const int64_t blocks = (3 * N + 255) / 256;
+    hipLaunchKernelGGL(k_turns, dim3((unsigned)blocks), dim3(256), 0, s, pos, 3 * N, 1.0 / L, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ force table pack
+// Per-row scale: the power of two at or above the row's largest |entry| (1
+// for an all-zero row), so that every row enters FP16 with magnitude <= 1 and
+// small rows keep their own relative precision; power-of-two scaling is exact.
+__global__ void __launch_bounds__(256)
+k_row_scale(const float *__restrict__ ftab, int n, int R, int nzp, float *__restrict__ rs)
+{
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= R) return;
+    float m = 0.f;
+    const float *f = ftab + (int64_t)r * nzp * 8;
+    for (int i = 0; i < n * 8; ++i) m = fmaxf(m, fabsf(f[i]));
+    int e = 0;
+    if (m > 0.f) {
+        frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+    }
+    rs[r] = m > 0.f ? ldexpf(1.0f, e) : 1.0f;
+}
+
+// W fragments: wf[t][s][h][lane][8] halves, t = row quad (rows 4t..4t+3),
+// s = K step, h = hi/lo.  Lane l, element i: A row m = l % 16 -> row 4t + m/4,
+// component m % 4; K index k = 32 s + 8 (l/16) + i -> cos (k < nzk) or sin of
+// n_z = (k mod nzk) + 1.
+__global__ void __launch_bounds__(256)
+k_force_pack(const float *__restrict__ ftab, const float *__restrict__ rs, int n, int R, int nzp,
+             int nzk, int quads, int ks, _Float16 *__restrict__ wf)
+{
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)quads * ks * 64;
+    if (gid >= total) return;
+    const int lane = (int)(gid & 63);
+    const int64_t ts = gid >> 6;
+    const int s = (int)(ts % ks);
+    const int t = (int)(ts / ks);
+    const int m = lane & 15;
+    const int r = 4 * t + (m >> 2);
+    const int e = m & 3;
+    const float inv = r < R ? 1.0f / rs[r] : 1.0f;
+    _Float16 hi[8], lo[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = 32 * s + 8 * (lane >> 4) + i;
+        const bool is_sin = k >= nzk;
+        const int nz = (is_sin ? k - nzk : k) + 1;
+        float v = 0.f;
+        if (r < R && nz <= n) {
+            const float *f = ftab + ((int64_t)r * nzp + (nz - 1)) * 8;
+            // f: sig_r sig_i del_r del_i nz*del_r nz*del_i nz*sig_r nz*sig_i
+            switch (e) {
+            case 0: v = is_sin ? -f[3] : f[0]; break;  // Re U0: sig_r cos - del_i sin
+            case 1: v = is_sin ? f[2] : f[1]; break;   // Im U0: sig_i cos + del_r sin
+            case 2: v = is_sin ? -f[7] : f[4]; break;  // Re U1: nz (del_r cos - sig_i sin)
+            default: v = is_sin ? f[6] : f[5]; break;  // Im U1: nz (del_i cos + sig_r sin)
+            }
+        }
+        split_f16(v * inv, hi[i], lo[i]);
+    }
+    _Float16 *o = wf + ((((int64_t)t * ks + s) * 2) * 64 + lane) * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        o[i] = hi[i];
+        o[64 * 8 + i] = lo[i];
+    }
+}
+
+hipError_t launch_force_pack(hipStream_t s, const float *ftab, const Geom &g, float *rowscale,
+                             _Float16 *wf)
+{
+    hipLaunchKernelGGL(k_row_scale, dim3((g.R + 255) / 256), dim3(256), 0, s, ftab, g.n, g.R, g.nzp,
+                       rowscale);
+    const int quads = (g.R + 3) / 4;
+    const int nzk = (g.n + 15) / 16 * 16;
+    const int ks = nzk / 16;
+    const int64_t total = (int64_t)quads * ks * 64;
+    hipLaunchKernelGGL(k_force_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ftab,
+                       rowscale, g.n, g.R, g.nzp, nzk, quads, ks, wf);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ force
+// Block = 4 waves x 64 particles (NT = 4 N tiles of 16 particles per wave).
+// The W fragments of TM row quads at a time are staged in LDS for the whole
+// block; every wave keeps its particles' CS fragments in registers.  The lane
+// group g = l/16 handles row 4t + g of each quad t, so the four groups sum
+// disjoint rows of the same particles and are combined at the end.
+constexpr int kForceTM = 8;
+
+template <int KS>
+__global__ void __launch_bounds__(256)
+k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
+             const double *__restrict__ m, double *__restrict__ vel, const _Float16 *__restrict__ wf,
+             const float *__restrict__ psi0, const float *__restrict__ rowscale, int n, int R,
+             int quads, double invL, int64_t N, double kick, double *__restrict__ F,
+             double *__restrict__ phi)
+{
+    constexpr int NT = 4;
+    extern __shared__ __align__(16) unsigned char smem[];
+    half8 *wl = reinterpret_cast<half8 *>(smem);  // [TM][KS][2][64]
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int g = lane >> 4;
+    const int ln = lane & 15;
+    const int nzk = 16 * KS;
+
+    // per N tile: particle, turns, CS fragments, phase state
+    half8 bh[NT][KS], bl[NT][KS];
+    double tx[NT], ty[NT];
+    float gc[NT], gs[NT], e4c[NT], e4s[NT];
+    double fx[NT], fy[NT], fz[NT], fp[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int64_t j = (int64_t)blockIdx.x * 256 + wave * 64 + nt * 16 + ln;
+        const int64_t jc = j < N ? j : N - 1;
+        tx[nt] = frac(pos[jc] * invL);
+        ty[nt] = frac(pos[N + jc] * invL);
+        const double tz = frac(pos[2 * N + jc] * invL);
+        double ezc, ezs;
+        cis_turns(tz, ezc, ezs);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            // k = 32 s + 8 g + i: cos for k < nzk, else sin; n_z consecutive in i
+            const int k0 = 32 * s + 8 * g;
+            const bool is_sin = k0 >= nzk;
+            const int nz0 = (is_sin ? k0 - nzk : k0) + 1;
+            double c, sn;
+            cis_turns(frac_mul(nz0, tz), c, sn);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                _Float16 h, l;
+                split_f16((float)(is_sin ? sn : c), h, l);
+                bh[nt][s][i] = h;
+                bl[nt][s][i] = l;
+                const double t = c * ezc - sn * ezs;
+                sn = sn * ezc + c * ezs;
+                c = t;
+            }
+        }
+        double a, b;
+        cis_turns(frac_mul(4, ty[nt]), a, b);
+        e4c[nt] = (float)a;
+        e4s[nt] = (float)b;
+        fx[nt] = fy[nt] = fz[nt] = fp[nt] = 0.0;
+    }
+    // lane group g starts at row g
+    int r = g;
+    int nx, ny;
+    row_nxny(r < R ? r : R - 1, n, nx, ny);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        double a, b;
+        cis_turns(frac_lin(nx, tx[nt], ny, ty[nt]), a, b);
+        gc[nt] = (float)a;
+        gs[nt] = (float)b;
+    }
+
+    for (int t0 = 0; t0 < quads; t0 += kForceTM) {
+        const int tcnt = quads - t0 < kForceTM ? quads - t0 : kForceTM;
+        __syncthreads();
+        {
+            const half8 *src = reinterpret_cast<const half8 *>(wf) + (int64_t)t0 * KS * 2 * 64;
+            const int total = tcnt * KS * 2 * 64;
+            for (int i = tid; i < total; i += 256) wl[i] = src[i];
+        }
+        __syncthreads();
+        for (int tt = 0; tt < tcnt; ++tt) {
+            half8 ah[KS], al[KS];
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                ah[s] = wl[((tt * KS + s) * 2 + 0) * 64 + lane];
+                al[s] = wl[((tt * KS + s) * 2 + 1) * 64 + lane];
+            }
+            const bool rv = r < R;
+            float p0r = 0.f, p0i = 0.f, wscale = 0.f;
+            if (rv) {
+                p0r = psi0[2 * r];
+                p0i = psi0[2 * r + 1];
+                wscale = rowscale[r];
+            }
+            const double dnx = (double)nx, dny = (double)ny;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) acc = mfma_split(ah[s], al[s], bh[nt][s], bl[nt][s], acc);
+                const float u0r = acc[0] * wscale + p0r, u0i = acc[1] * wscale + p0i;
+                const float u1r = acc[2] * wscale, u1i = acc[3] * wscale;
+                const double im0 = (double)(gc[nt] * u0i + gs[nt] * u0r);
+                const double re0 = (double)(gc[nt] * u0r - gs[nt] * u0i);
+                const double im1 = (double)(gc[nt] * u1i + gs[nt] * u1r);
+                fx[nt] = fma(dnx, im0, fx[nt]);
+                fy[nt] = fma(dny, im0, fy[nt]);
+                fz[nt] += im1;
+                fp[nt] += re0;
+            }
+            // next row of this lane group: r + 4
+            r += 4;
+            int nnx, nny;
+            row_nxny(r < R ? r : R - 1, n, nnx, nny);
+            if (nnx == nx) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const float c = gc[nt] * e4c[nt] - gs[nt] * e4s[nt];
+                    gs[nt] = gs[nt] * e4c[nt] + gc[nt] * e4s[nt];
+                    gc[nt] = c;
+                }
+            } else {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    double a, b;
+                    cis_turns(frac_lin(nnx, tx[nt], nny, ty[nt]), a, b);
+                    gc[nt] = (float)a;
+                    gs[nt] = (float)b;
+                }
+            }
+            nx = nnx;
+            ny = nny;
+        }
+    }
+    // combine the four lane groups (same particles, disjoint rows)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        for (int o = 16; o <= 32; o <<= 1) {
+            fx[nt] += __shfl_xor(fx[nt], o, 64);
+            fy[nt] += __shfl_xor(fy[nt], o, 64);
+            fz[nt] += __shfl_xor(fz[nt], o, 64);
+            fp[nt] += __shfl_xor(fp[nt], o, 64);
+        }
+        const int64_t j = (int64_t)blockIdx.x * 256 + wave * 64 + nt * 16 + ln;
+        if (g == 0 && j < N) {
+            const double f = 2.0 * q[j] * (6.283185307179586476925286766559 * invL);
+            const double Fx = f * fx[nt], Fy = f * fy[nt], Fz = f * fz[nt];
+            if (F) {
+                F[j] = Fx;
+                F[N + j] = Fy;
+                F[2 * N + j] = Fz;
+            }
+            if (phi) phi[j] = 2.0 * fp[nt];
+            if (kick != 0.0) {
+                const double a = kick / m[j];
+                vel[j] += a * Fx;
+                vel[N + j] += a * Fy;
+                vel[2 * N + j] += a * Fz;
+            }
+        }
+    }
+}
+
+hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, const double *m,
+                             double *vel, const _Float16 *wf, const float *psi0, const float *rowscale,
+                             const Geom &g, double L, int64_t N, double kick, double *F,
+                             double *phi)
+{
+    const int quads = (g.R + 3) / 4;
+    const int ks = (g.n + 15) / 16;
+    const int64_t blocks = (N + 255) / 256;
+    const size_t lds = (size_t)kForceTM * ks * 2 * 64 * sizeof(half8);
+    switch (ks) {
+    case 1:
+        hipLaunchKernelGGL(k_force_mfma<1>, dim3((unsigned)blocks), dim3(256), lds, s, pos, q, m,
+                           vel, wf, psi0, rowscale, g.n, g.R, quads, 1.0 / L, N, kick, F, phi);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_force_mfma<2>, dim3((unsigned)blocks), dim3(256), lds, s, pos, q, m,
+                           vel, wf, psi0, rowscale, g.n, g.R, quads, 1.0 / L, N, kick, F, phi);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_force_mfma<3>, dim3((unsigned)blocks), dim3(256), lds, s, pos, q, m,
+                           vel, wf, psi0, rowscale, g.n, g.R, quads, 1.0 / L, N, kick, F, phi);
+        break;
+    default:
+        hipLaunchKernelGGL(k_force_mfma<4>, dim3((unsigned)blocks), dim3(256), lds, s, pos, q, m,
+                           vel, wf, psi0, rowscale, g.n, g.R, quads, 1.0 / L, N, kick, F, phi);
+        break;
+    }
+    return hipGetLastError();
+}
+
+size_t force_pack_bytes(const Geom &g)
+{
+    const int quads = (g.R + 3) / 4;
+    const int ks = (g.n + 15) / 16;
+    return (size_t)quads * ks * 2 * 64 * 8 * sizeof(_Float16);
+}
+
+}  // namespace sce

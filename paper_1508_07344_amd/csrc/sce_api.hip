@@ -51,6 +51,12 @@ struct sce_ctx_s {
     double *Stab = nullptr, *Gtab = nullptr, *Ktab = nullptr;
     double2 *rho = nullptr, *psi = nullptr;
     void *ftab = nullptr, *psi0 = nullptr;
+    // split-precision path: positions in turns, packed force fragments, scale scratch
+    double *turns = nullptr;
+    size_t turns_bytes = 0;
+    void *wf = nullptr;
+    float *wscr = nullptr;
+    double qscale = 1.0;
     double *wpart = nullptr;
     int wblocks = 0;
     double *dscratch = nullptr;
@@ -195,6 +201,12 @@ sce_status alloc_prec_buffers(sce_ctx c)
     HIPCHK(c, hipMalloc(&c->ftab, fbytes));
     HIPCHK(c, hipMemset(c->ftab, 0, fbytes));
     HIPCHK(c, hipMalloc(&c->psi0, (size_t)c->g.R * 2 * eb));
+    free_dev(c->wf);
+    free_devp(c->wscr);
+    if (c->prec == SCE_PREC_SPLIT_F16) {
+        HIPCHK(c, hipMalloc(&c->wf, sce::force_pack_bytes(c->g)));
+        HIPCHK(c, dev_alloc(c->wscr, (size_t)c->g.R * sizeof(float)));
+    }
     return SCE_OK;
 }
 
@@ -294,10 +306,65 @@ sce_status run_force(sce_ctx c, double kick)
     return SCE_OK;
 }
 
+sce_status run_deposit_split(sce_ctx c)
+{
+    const Geom &g = c->g;
+    const sce::MfmaDepositPlan pl = sce::plan_deposit_mfma(g, c->N);
+    void *tp = c->turns;
+    sce_status st = ensure_bytes(c, tp, c->turns_bytes, (size_t)3 * c->N * sizeof(double));
+    c->turns = (double *)tp;
+    if (st) return st;
+    size_t pb = c->part_bytes;
+    void *pp = c->part;
+    st = ensure_bytes(c, pp, pb, (size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(double));
+    c->part = (double *)pp;
+    c->part_bytes = pb;
+    if (st) return st;
+    HIPCHK(c, sce::launch_turns(c->stream, c->pos, c->N, c->L, c->turns));
+    EventPair ep{nullptr, nullptr};
+    if (c->timing) {
+        ep.a = take_event(c);
+        ep.b = take_event(c);
+        if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
+    }
+    HIPCHK(c, sce::launch_deposit_mfma(c->stream, c->turns, c->q, c->N, g, pl, c->qscale, c->part));
+    if (c->timing && ep.a && ep.b) {
+        HIPCHK(c, hipEventRecord(ep.b, c->stream));
+        c->ev_dep.push_back(ep);
+    }
+    HIPCHK(c, sce::launch_reduce_solve<float>(c->stream, c->part, pl.splits, g, c->Stab, c->Gtab,
+                                              c->Ktab, c->rho, c->psi, (float *)c->ftab,
+                                              (float *)c->psi0, c->wpart, &c->wblocks));
+    HIPCHK(c, sce::launch_force_pack(c->stream, (const float *)c->ftab, g, c->wscr,
+                                     (_Float16 *)c->wf));
+    c->fields_valid = true;
+    return SCE_OK;
+}
+
+sce_status run_force_split(sce_ctx c, double kick)
+{
+    EventPair ep{nullptr, nullptr};
+    if (c->timing) {
+        ep.a = take_event(c);
+        ep.b = take_event(c);
+        if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
+    }
+    HIPCHK(c, sce::launch_force_mfma(c->stream, c->pos, c->q, c->m, c->vel, (const _Float16 *)c->wf,
+                                     (const float *)c->psi0, c->wscr, c->g, c->L, c->N, kick, c->F,
+                                     c->phi));
+    if (c->timing && ep.a && ep.b) {
+        HIPCHK(c, hipEventRecord(ep.b, c->stream));
+        c->ev_frc.push_back(ep);
+    }
+    c->force_valid = true;
+    return SCE_OK;
+}
+
 sce_status deposit(sce_ctx c)
 {
     if (c->prec == SCE_PREC_FP64) return run_deposit<double>(c);
     if (c->prec == SCE_PREC_FP32) return run_deposit<float>(c);
+    if (c->prec == SCE_PREC_SPLIT_F16) return run_deposit_split(c);
     return fail(c, SCE_ENOTSUP, "precision not available");
 }
 
@@ -305,6 +372,7 @@ sce_status force(sce_ctx c, double kick)
 {
     if (c->prec == SCE_PREC_FP64) return run_force<double>(c, kick);
     if (c->prec == SCE_PREC_FP32) return run_force<float>(c, kick);
+    if (c->prec == SCE_PREC_SPLIT_F16) return run_force_split(c, kick);
     return fail(c, SCE_ENOTSUP, "precision not available");
 }
 
@@ -406,7 +474,6 @@ sce_status sce_set_options(sce_ctx c, double eps0, int32_t precision, int32_t sc
     if (!(eps0 > 0.0) || !std::isfinite(eps0)) return fail(c, SCE_EINVAL, "eps0 must be finite and > 0");
     if (precision < SCE_PREC_FP64 || precision > SCE_PREC_SPLIT_F16)
         return fail(c, SCE_EINVAL, "unknown precision");
-    if (precision == SCE_PREC_SPLIT_F16) return fail(c, SCE_ENOTSUP, "split-precision path not built");
     if (scheme != SCE_SCHEME_KDK && scheme != SCE_SCHEME_DKD) return fail(c, SCE_EINVAL, "unknown scheme");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const bool prec_changed = precision != c->prec;
@@ -452,9 +519,13 @@ sce_status sce_set_particles(sce_ctx c, int64_t N, const double *x, const double
     std::vector<double> hq(N);
     HIPCHK(c, hipMemcpyAsync(hq.data(), c->q, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double s = 0.0;
-    for (double v_ : hq) s += v_ * v_;
+    double s = 0.0, qmax = 0.0;
+    for (double v_ : hq) {
+        s += v_ * v_;
+        qmax = std::fmax(qmax, std::fabs(v_));
+    }
     c->q2sum = s;
+    c->qscale = qmax > 0.0 ? qmax : 1.0;
     c->step = 0;
     c->time = 0.0;
     c->fields_valid = c->force_valid = false;
@@ -724,6 +795,9 @@ void sce_destroy(sce_ctx c)
     free_devp(c->psi);
     free_dev(c->ftab);
     free_dev(c->psi0);
+    free_dev(c->wf);
+    free_devp(c->wscr);
+    free_devp(c->turns);
     free_devp(c->wpart);
     free_devp(c->dscratch);
     free_devp(c->dout);

@@ -1,0 +1,31 @@
+// Device helpers shared by the direct and matrix-core kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sce {
+
+__device__ inline double frac(double t) { return t - floor(t); }
+
+// frac(k t) with the product formed exactly (two-product) before reduction.
+__device__ inline double frac_mul(int k, double t)
+{
+    const double hi = (double)k * t;
+    const double lo = fma((double)k, t, -hi);
+    const double u = (hi - floor(hi)) + lo;
+    return u - floor(u);
+}
+
+// frac(a ta + b tb), each product exact before reduction.
+__device__ inline double frac_lin(int a, double ta, int b, double tb)
+{
+    const double h1 = (double)a * ta, l1 = fma((double)a, ta, -h1);
+    const double h2 = (double)b * tb, l2 = fma((double)b, tb, -h2);
+    const double u = (h1 - floor(h1)) + (h2 - floor(h2)) + (l1 + l2);
+    return u - floor(u);
+}
+
+// (cos, sin)(2 pi u)
+__device__ inline void cis_turns(double u, double &c, double &s) { sincospi(2.0 * u, &s, &c); }
+
+}  // namespace sce

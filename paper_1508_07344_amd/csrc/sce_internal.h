@@ -95,6 +95,31 @@ hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const
                         double *vel, const T *ftab, const T *psi0, const Geom &g, double L,
                         int64_t N, double kick, double *F, double *phi);
 
+// ---- split-precision matrix-core path (kernels_mfma.hip)
+struct MfmaDepositPlan {
+    int row_blocks;     // ceil(R / 256)
+    int splits;
+    int64_t per_split;
+    int64_t perm;       // half width h of the Feistel visiting order (2^(2h) >= N)
+};
+MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N);
+// positions in turns t = frac(x / L), [3][N]
+hipError_t launch_turns(hipStream_t s, const double *pos, int64_t N, double L, double *out);
+// Deposit partial sums (same layout as launch_deposit) from positions in turns;
+// charges are scaled by 1/qscale inside and the partials by qscale.
+hipError_t launch_deposit_mfma(hipStream_t s, const double *pos_turns, const double *q, int64_t N,
+                               const Geom &g, const MfmaDepositPlan &pl, double qscale,
+                               double *part);
+// Pack the FP32 force table into FP16 hi/lo matrix-core fragments, each row
+// scaled by its power-of-two scale rowscale[r] (R floats, written here).
+size_t force_pack_bytes(const Geom &g);
+hipError_t launch_force_pack(hipStream_t s, const float *ftab, const Geom &g, float *rowscale,
+                             _Float16 *wf);
+hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, const double *m,
+                             double *vel, const _Float16 *wf, const float *psi0, const float *rowscale,
+                             const Geom &g, double L, int64_t N, double kick, double *F,
+                             double *phi);
+
 // v += a F/m (if a != 0); x = wrap(x + b v) (if b != 0).
 hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *F,
                              const double *m, int64_t N, double L, double a, double b);

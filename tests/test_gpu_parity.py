@@ -8,7 +8,9 @@ modes whose rho is near zero):
 Tolerances: FP64 path <= 1e-12.  FP32 path: the phase tables are exact to
 FP32 rounding (u = 2^-24) and each product and running sum adds a few u, so
 the normwise error of either sum is O(10 u) ~ 1e-6 at these sizes; the tests
-use 1e-5, the accuracy asked of the force.
+use 1e-5, the accuracy asked of the force.  Split FP16 path: each operand
+carried as hi + lo halves (22 significant bits), the dropped lo*lo term is
+~2^-22 relative, accumulation is FP32: same 1e-5 bound.
 """
 import math
 import os
@@ -21,7 +23,8 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-5}
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "split_f16": 1e-5}
+PRECS = ["fp64", "fp32", "split_f16"]
 
 
 def _gpu():
@@ -64,7 +67,7 @@ def references():
     return out
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("name", [c[0] for c in _cases()])
 def test_deposit_and_force_match_oracle(references, name, prec):
     sce = _gpu()
@@ -89,7 +92,7 @@ def test_deposit_and_force_match_oracle(references, name, prec):
     assert abs(d.interaction - 2 * ref.W) <= (1e-12 if prec == "fp64" else 1e-5) * abs(ref.W)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_random_plasma_full_size_sampled(prec):
     """N = 65536, n_max = 16: rho on sampled modes, F on sampled particles
     (the oracle's F needs its own full rho, computed once)."""
@@ -114,7 +117,7 @@ def test_random_plasma_full_size_sampled(prec):
     assert err <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_cold_lattice_full_size(prec):
     """N = 1,048,576 lattice, n_max = 32: rho on sampled modes (including the
     perturbed one) against the oracle; F through properties that hold at any
@@ -138,17 +141,18 @@ def test_cold_lattice_full_size(prec):
     assert abs(d.interaction - 2 * d.field) <= (1e-12 if prec == "fp64" else 1e-5) * abs(d.field)
 
 
-def test_fp32_matches_fp64_gpu_at_full_size():
-    """Same inputs, FP32 vs FP64 GPU path, N = 1,048,576, n_max = 32."""
+@pytest.mark.parametrize("prec", ["fp32", "split_f16"])
+def test_reduced_precision_matches_fp64_gpu_at_full_size(prec):
+    """Same inputs, FP32 or split-FP16 vs the FP64 GPU path, N = 1,048,576, n_max = 32."""
     sce = _gpu()
     p = workloads.cold_lattice()
     out = {}
-    for prec in ("fp64", "fp32"):
-        with sce.Context.from_particles(p, precision=prec) as c:
-            out[prec] = (c.sce_deposit(), c.sce_force())
-    er = e_rho(out["fp32"][0], out["fp64"][0])
-    ef = e_F(out["fp32"][1], out["fp64"][1])
-    print(f"lattice fp32 vs fp64: e_rho={er:.3e} e_F={ef:.3e}")
+    for pr in ("fp64", prec):
+        with sce.Context.from_particles(p, precision=pr) as c:
+            out[pr] = (c.sce_deposit(), c.sce_force())
+    er = e_rho(out[prec][0], out["fp64"][0])
+    ef = e_F(out[prec][1], out["fp64"][1])
+    print(f"lattice {prec} vs fp64: e_rho={er:.3e} e_F={ef:.3e}")
     assert er <= 1e-5 and ef <= 1e-5
 
 
@@ -188,7 +192,7 @@ def test_two_body_trajectory_matches_oracle(scheme, steps):
     assert np.max(np.abs(d.momentum)) <= 1e-12 * d.momentum_abs_sum
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_short_plasma_run_matches_oracle(prec):
     sce = _gpu()
     p = workloads.random_plasma(N=512, n_max=8, a=0.05, sigma_v=0.05)
