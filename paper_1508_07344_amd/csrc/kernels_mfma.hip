@@ -94,24 +94,69 @@ constexpr float kDepOpScale = 0.875f;
 // the running sum is much larger than each increment, slightly toward -inf.
 // Over thousands of chunks that directional bias is identical in every
 // accumulator and would act like a spurious charge at the origin.  The running
-// sum therefore changes sign every chunk (accumulator and CS operand negated
-// together), so the bias alternates direction and cancels.
+// sum therefore changes sign every 4 chunks (accumulator and CS operand
+// negated together), so the bias alternates direction and cancels.
 
+// Per-particle record in visiting order, FP32, for nb = ceil((n+1)/8) blocks
+// of 8 powers per axis: [d][blk] = cis(2 pi 8 blk t_d) (anchors, formed in
+// FP64), then [d] = cis(2 pi t_d) (steps), then the scaled charge
+// (q / max|q|) * 7/8; padded to a multiple of 4 floats.
+__host__ __device__ inline int dep_rec_floats(int n)
+{
+    const int nb = (n + 1 + 7) / 8;
+    return (3 * (nb + 1) * 2 + 1 + 3) / 4 * 4;
+}
+
+__global__ void __launch_bounds__(256)
+k_deposit_prep(const double *__restrict__ pos, const double *__restrict__ q, int64_t N, int n,
+               double invL, int h, double qfac, float *__restrict__ rec)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const int nb = (n + 1 + 7) / 8;
+    const int64_t j = feistel_perm((uint32_t)i, (uint32_t)N, h);
+    float *o = rec + i * dep_rec_floats(n);
+    for (int d = 0; d < 3; ++d) {
+        const double t = frac(pos[d * N + j] * invL);
+        for (int blk = 0; blk < nb; ++blk) {
+            double c, sn;
+            cis_turns(frac_mul(8 * blk, t), c, sn);
+            o[2 * (d * nb + blk)] = (float)c;
+            o[2 * (d * nb + blk) + 1] = (float)sn;
+        }
+        double c, sn;
+        cis_turns(t, c, sn);
+        o[2 * (3 * nb + d)] = (float)c;
+        o[2 * (3 * nb + d) + 1] = (float)sn;
+    }
+    o[6 * (nb + 1)] = (float)(q[j] * qfac);
+}
+
+// Table row of particle p in the LDS a/b tables: groups of 8 particles are
+// separated by 4 float2 of padding so that the four lane groups (particles
+// 8g..8g+7) read from distinct banks.
+__device__ inline int tab_row(int p, int n1) { return p * n1 + (p >> 3) * 4; }
+
+// Block = 8 waves = 256 rows (two 16-row N tiles per wave), all CS rows
+// (MT tiles of 16); blockIdx.y = particle split.  Per chunk of 32 particles
+// the block builds LDS tables from the particle records (each thread's record
+// fields prefetched one chunk ahead): a = q cis(-nx tx), b = cis(-k ty) (FP32)
+// and the CS operand as FP16 hi/lo; each lane then forms its own H fragment.
 template <int MT>
 __global__ void __launch_bounds__(512)
-k_deposit_mfma(const double *__restrict__ pos /* turns */, const double *__restrict__ q, int64_t N, int n,
-               int R, int Rpad, int64_t perm, int64_t per_split, double qinv, double qscale,
-               double *__restrict__ part)
+k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
+               int64_t per_split, double unscale, double *__restrict__ part)
 {
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    typedef float float2_t __attribute__((ext_vector_type(2)));
     extern __shared__ __align__(16) unsigned char smem[];
     const int n1 = n + 1;
     const int CSR = MT * 16;  // CS rows incl. padding
+    const int trows = kDepChunk * n1 + 16;
     _Float16 *cs_hi = reinterpret_cast<_Float16 *>(smem);            // [CSR][32]
     _Float16 *cs_lo = cs_hi + CSR * kDepChunk;                        // [CSR][32]
-    float2 *ta = reinterpret_cast<float2 *>(cs_lo + CSR * kDepChunk);  // [32][n1]
-    float2 *tb = ta + kDepChunk * n1;                                 // [32][n1]
-    double2 *c1 = reinterpret_cast<double2 *>(tb + kDepChunk * n1);    // [32][3] cis(t_d)
-    double *tq = reinterpret_cast<double *>(c1 + kDepChunk * 3);      // [32] scaled charges
+    float2 *ta = reinterpret_cast<float2 *>(cs_lo + CSR * kDepChunk);  // tab_row(p) + k
+    float2 *tb = ta + trows;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -120,14 +165,14 @@ k_deposit_mfma(const double *__restrict__ pos /* turns */, const double *__restr
     const int ln = lane & 15;  // row within an N tile
     const int64_t j0 = (int64_t)blockIdx.y * per_split;
     const int64_t j1 = j0 + per_split < N ? j0 + per_split : N;
+    const int nb = (n1 + 7) / 8;
+    const int rf = dep_rec_floats(n);
 
-    // zero CS padding rows once (never written afterwards)
     for (int idx = tid; idx < (CSR - (2 * n + 1)) * kDepChunk; idx += 512) {
         cs_hi[(2 * n + 1) * kDepChunk + idx] = (_Float16)0.0f;
         cs_lo[(2 * n + 1) * kDepChunk + idx] = (_Float16)0.0f;
     }
 
-    // this lane's two rows
     int rnx[2], rny[2];
     bool rok[2];
 #pragma unroll
@@ -143,124 +188,162 @@ k_deposit_mfma(const double *__restrict__ pos /* turns */, const double *__restr
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) acc[mt][nt][0] = acc[mt][nt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    const int nb = (n1 + 7) / 8;  // blocks of 8 powers per axis
-
-    for (int64_t base = j0; base < j1; base += kDepChunk) {
-        const int cnt = (int)((j1 - base) < kDepChunk ? (j1 - base) : kDepChunk);
-        const bool odd = (((base - j0) / kDepChunk) & 1) != 0;
-        const float csg = odd ? -kDepOpScale : kDepOpScale;
-        __syncthreads();  // previous chunk's tables are no longer read
-        // 1. fundamental phases cis(2 pi t_d) and scaled charges
-        if (tid < 3 * kDepChunk) {
-            const int p = tid / 3, d = tid - 3 * (tid / 3);
-            double cc = 1.0, ss = 0.0;
-            if (p < cnt) {
-                const int64_t jp = feistel_perm((uint32_t)(base + p), (uint32_t)N, (int)perm);
-                cis_turns(pos[d * N + jp], cc, ss);  // positions in turns
-                if (d == 0) tq[p] = q[jp] * qinv * (double)kDepOpScale;
-            } else if (d == 0) {
-                tq[p] = 0.0;
-            }
-            c1[p * 3 + d] = make_double2(cc, ss);
+    // table tasks (axis d, block blk, particle p), particle fastest
+    const int ntask = 3 * nb * kDepChunk;
+    const int t_p = tid & (kDepChunk - 1);
+    const int t_db = tid / kDepChunk;
+    const int t_d = t_db / nb, t_blk = t_db - t_d * nb;
+    float pa_c = 1.f, pa_s = 0.f, ps_c = 1.f, ps_s = 0.f, pq = 0.f;
+    auto fetch = [&](int64_t cbase) {
+        pa_c = 1.f;
+        pa_s = 0.f;
+        ps_c = 1.f;
+        ps_s = 0.f;
+        pq = 0.f;
+        if (tid < ntask && cbase + t_p < j1) {
+            const float *r0 = rec + (cbase + t_p) * rf;
+            pa_c = r0[2 * (t_d * nb + t_blk)];
+            pa_s = r0[2 * (t_d * nb + t_blk) + 1];
+            ps_c = r0[2 * (3 * nb + t_d)];
+            ps_s = r0[2 * (3 * nb + t_d) + 1];
+            pq = r0[6 * (nb + 1)];
         }
-        __syncthreads();
-        // 2. tables: task = (particle, axis, block of 8 powers)
-        for (int task = tid; task < kDepChunk * 3 * nb; task += 512) {
-            const int p = task / (3 * nb);
-            const int rem = task - p * 3 * nb;
-            const int d = rem / nb, blk = rem - d * nb;
-            const double2 e = c1[p * 3 + d];
-            // anchor cis(8 blk t) by repeated squaring of cis(t)
-            double ac = 1.0, as = 0.0;
-            {
-                double pc = e.x, ps = e.y;
-                int k = 8 * blk;
-                while (k) {
-                    if (k & 1) {
-                        const double t = ac * pc - as * ps;
-                        as = ac * ps + as * pc;
-                        ac = t;
-                    }
-                    const double t = pc * pc - ps * ps;
-                    ps = 2.0 * pc * ps;
-                    pc = t;
-                    k >>= 1;
+    };
+    fetch(j0);
+
+    int64_t chunk = 0;
+    for (int64_t base = j0; base < j1; base += kDepChunk, ++chunk) {
+        const bool neg = ((chunk >> 2) & 1) != 0;
+        const float csg = neg ? -kDepOpScale : kDepOpScale;
+        __syncthreads();  // previous chunk's tables are no longer read
+        for (int task = tid; task < ntask; task += 512) {
+            int p, d, blk;
+            float fc, fs, sc, ss, fq;
+            if (task == tid) {
+                p = t_p;
+                d = t_d;
+                blk = t_blk;
+                fc = pa_c;
+                fs = pa_s;
+                sc = ps_c;
+                ss = ps_s;
+                fq = pq;
+            } else {
+                p = task & (kDepChunk - 1);
+                const int db = task / kDepChunk;
+                d = db / nb;
+                blk = db - d * nb;
+                fc = 1.f;
+                fs = 0.f;
+                sc = 1.f;
+                ss = 0.f;
+                fq = 0.f;
+                if (base + p < j1) {
+                    const float *r0 = rec + (base + p) * rf;
+                    fc = r0[2 * (d * nb + blk)];
+                    fs = r0[2 * (d * nb + blk) + 1];
+                    sc = r0[2 * (3 * nb + d)];
+                    ss = r0[2 * (3 * nb + d) + 1];
+                    fq = r0[6 * (nb + 1)];
                 }
             }
-            const double qq = tq[p];
-            for (int kk = 0; kk < 8; ++kk) {
-                const int k = 8 * blk + kk;
-                if (k > n) break;
-                if (d == 0) {
-                    ta[p * n1 + k] = make_float2((float)(qq * ac), (float)(-qq * as));
-                } else if (d == 1) {
-                    tb[p * n1 + k] = make_float2((float)ac, (float)(-as));
-                } else {
+            const int k0 = 8 * blk;
+            const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
+            if (d == 0) {
+                float2 *dst = ta + tab_row(p, n1) + k0;
+                for (int kk = 0; kk < kend; ++kk) {
+                    dst[kk] = make_float2(fq * fc, -fq * fs);
+                    const float t = fc * sc - fs * ss;
+                    fs = fc * ss + fs * sc;
+                    fc = t;
+                }
+            } else if (d == 1) {
+                float2 *dst = tb + tab_row(p, n1) + k0;
+                for (int kk = 0; kk < kend; ++kk) {
+                    dst[kk] = make_float2(fc, -fs);
+                    const float t = fc * sc - fs * ss;
+                    fs = fc * ss + fs * sc;
+                    fc = t;
+                }
+            } else {
+                for (int kk = 0; kk < kend; ++kk) {
+                    const int k = k0 + kk;
                     _Float16 h, l;
-                    split_f16((float)(csg * ac), h, l);
+                    split_f16(csg * fc, h, l);
                     cs_hi[k * kDepChunk + p] = h;
                     cs_lo[k * kDepChunk + p] = l;
                     if (k > 0) {
-                        split_f16((float)(csg * as), h, l);
+                        split_f16(csg * fs, h, l);
                         cs_hi[(n + k) * kDepChunk + p] = h;
                         cs_lo[(n + k) * kDepChunk + p] = l;
                     }
+                    const float t = fc * sc - fs * ss;
+                    fs = fc * ss + fs * sc;
+                    fc = t;
                 }
-                const double t = ac * e.x - as * e.y;
-                as = ac * e.y + as * e.x;
-                ac = t;
             }
         }
+        fetch(base + kDepChunk);
         __syncthreads();
-        // 3. H fragments for this lane's two rows (particles 8g..8g+7)
-        half8 bre_h[2], bre_l[2], bim_h[2], bim_l[2];
+        if (chunk > 0 && (chunk & 3) == 0) {
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            const int ay = rny[nt] < 0 ? -rny[nt] : rny[nt];
-            const float sgn = rny[nt] < 0 ? -1.0f : 1.0f;
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int p = 8 * g + i;
-                const float2 a = ta[p * n1 + rnx[nt]];
-                float2 b = tb[p * n1 + ay];
-                b.y *= sgn;
-                float hr = a.x * b.x - a.y * b.y;
-                float hi = a.x * b.y + a.y * b.x;
-                if (!rok[nt]) hr = hi = 0.0f;
-                _Float16 x0, x1;
-                split_f16(hr, x0, x1);
-                bre_h[nt][i] = x0;
-                bre_l[nt][i] = x1;
-                split_f16(hi, x0, x1);
-                bim_h[nt][i] = x0;
-                bim_l[nt][i] = x1;
-            }
+                for (int nt = 0; nt < 2; ++nt) {
+                    acc[mt][nt][0] = -acc[mt][nt][0];
+                    acc[mt][nt][1] = -acc[mt][nt][1];
+                }
         }
-        // 4. matrix-core products over the chunk, running sum sign-alternated
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                acc[mt][nt][0] = -acc[mt][nt][0];
-                acc[mt][nt][1] = -acc[mt][nt][1];
-            }
+        half8 ah[MT], al[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            const half8 ah = *reinterpret_cast<const half8 *>(&cs_hi[(mt * 16 + ln) * kDepChunk + 8 * g]);
-            const half8 al = *reinterpret_cast<const half8 *>(&cs_lo[(mt * 16 + ln) * kDepChunk + 8 * g]);
+            ah[mt] = *reinterpret_cast<const half8 *>(&cs_hi[(mt * 16 + ln) * kDepChunk + 8 * g]);
+            al[mt] = *reinterpret_cast<const half8 *>(&cs_lo[(mt * 16 + ln) * kDepChunk + 8 * g]);
+        }
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                acc[mt][nt][0] = mfma_split(ah, al, bre_h[nt], bre_l[nt], acc[mt][nt][0]);
-                acc[mt][nt][1] = mfma_split(ah, al, bim_h[nt], bim_l[nt], acc[mt][nt][1]);
+        for (int nt = 0; nt < 2; ++nt) {
+            half8 bre_h, bre_l, bim_h, bim_l;
+            const int ay = rny[nt] < 0 ? -rny[nt] : rny[nt];
+            const float sgn = rny[nt] < 0 ? -1.0f : 1.0f;
+            const float zero = rok[nt] ? 1.0f : 0.0f;
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) {
+                const int p0 = 8 * g + i;
+                const float2 a0 = ta[tab_row(p0, n1) + rnx[nt]];
+                const float2 b0 = tb[tab_row(p0, n1) + ay];
+                const float2 a1 = ta[tab_row(p0 + 1, n1) + rnx[nt]];
+                const float2 b1 = tb[tab_row(p0 + 1, n1) + ay];
+                const float b0y = sgn * b0.y, b1y = sgn * b1.y;
+                float2_t hr, hm;
+                hr[0] = zero * (a0.x * b0.x - a0.y * b0y);
+                hm[0] = zero * (a0.x * b0y + a0.y * b0.x);
+                hr[1] = zero * (a1.x * b1.x - a1.y * b1y);
+                hm[1] = zero * (a1.x * b1y + a1.y * b1.x);
+                const half2_t rh = __builtin_convertvector(hr, half2_t);
+                const half2_t mh = __builtin_convertvector(hm, half2_t);
+                const half2_t rl = __builtin_convertvector(hr - __builtin_convertvector(rh, float2_t), half2_t);
+                const half2_t ml = __builtin_convertvector(hm - __builtin_convertvector(mh, float2_t), half2_t);
+                bre_h[i] = rh[0];
+                bre_h[i + 1] = rh[1];
+                bre_l[i] = rl[0];
+                bre_l[i + 1] = rl[1];
+                bim_h[i] = mh[0];
+                bim_h[i + 1] = mh[1];
+                bim_l[i] = ml[0];
+                bim_l[i + 1] = ml[1];
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                acc[mt][nt][0] = mfma_split(ah[mt], al[mt], bre_h, bre_l, acc[mt][nt][0]);
+                acc[mt][nt][1] = mfma_split(ah[mt], al[mt], bim_h, bim_l, acc[mt][nt][1]);
             }
         }
     }
 
-    // after chunk c (0-based) the accumulators hold (-1)^c times the sum
-    const int64_t nchunks = (j1 - j0 + kDepChunk - 1) / kDepChunk;
-    const double fsign = (nchunks & 1) ? 1.0 : -1.0;
-    qscale *= fsign;
-    // partial sums of this split: D[m][r], m = CS row, r = row (lane's ln)
+    // after chunk c the running sums carry the sign (-1)^((c >> 2) & 1)
+    const int64_t last = (j1 - j0 + kDepChunk - 1) / kDepChunk - 1;
+    const double fsign = ((last >> 2) & 1) ? -1.0 : 1.0;
+    const double outscale = unscale * fsign;
     double *pb = part + (int64_t)blockIdx.y * (int64_t)n1 * 4 * Rpad;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
@@ -281,8 +364,8 @@ k_deposit_mfma(const double *__restrict__ pos /* turns */, const double *__restr
                 } else {
                     continue;
                 }
-                pb[((int64_t)nz * 4 + slot) * Rpad + r] = qscale * (double)acc[mt][nt][0][i];
-                pb[((int64_t)nz * 4 + slot + 1) * Rpad + r] = qscale * (double)acc[mt][nt][1][i];
+                pb[((int64_t)nz * 4 + slot) * Rpad + r] = outscale * (double)acc[mt][nt][0][i];
+                pb[((int64_t)nz * 4 + slot + 1) * Rpad + r] = outscale * (double)acc[mt][nt][1][i];
                 if (m == 0) {
                     pb[((int64_t)0 * 4 + 2) * Rpad + r] = 0.0;
                     pb[((int64_t)0 * 4 + 3) * Rpad + r] = 0.0;
@@ -298,8 +381,7 @@ size_t deposit_mfma_lds(int n)
 {
     const int n1 = n + 1;
     return (size_t)mfma_cs_tiles(n) * 16 * kDepChunk * 2 * sizeof(_Float16) +
-           (size_t)2 * kDepChunk * n1 * sizeof(float2) + (size_t)kDepChunk * 3 * sizeof(double2) +
-           (size_t)kDepChunk * sizeof(double);
+           (size_t)2 * (kDepChunk * n1 + 16) * sizeof(float2);
 }
 
 MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
@@ -322,47 +404,34 @@ MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
 }
 
 template <int MT>
-static void launch_dep_mt(hipStream_t s, const double *pos, const double *q, int64_t N,
-                          const Geom &g, const MfmaDepositPlan &pl, double L, double qscale,
-                          double *part)
+static void launch_dep_mt(hipStream_t s, const float *rec, int64_t N, const Geom &g,
+                          const MfmaDepositPlan &pl, double unscale, double *part)
 {
-    (void)L;
-    const double unscale = qscale / ((double)kDepOpScale * (double)kDepOpScale);
     hipLaunchKernelGGL(k_deposit_mfma<MT>, dim3(pl.row_blocks, pl.splits), dim3(512),
-                       deposit_mfma_lds(g.n), s, pos, q, N, g.n, g.R, g.Rpad, pl.perm,
-                       pl.per_split, 1.0 / qscale, unscale, part);
+                       deposit_mfma_lds(g.n), s, rec, N, g.n, g.R, g.Rpad, pl.per_split, unscale,
+                       part);
 }
 
-hipError_t launch_deposit_mfma(hipStream_t s, const double *pos_turns, const double *q, int64_t N,
-                               const Geom &g, const MfmaDepositPlan &pl, double qscale,
-                               double *part)
+size_t deposit_mfma_rec_bytes(int64_t N, int n) { return (size_t)N * dep_rec_floats(n) * sizeof(float); }
+
+hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q, int64_t N,
+                               const Geom &g, double L, const MfmaDepositPlan &pl, double qscale,
+                               float *rec, double *part)
 {
+    hipLaunchKernelGGL(k_deposit_prep, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, pos, q,
+                       N, g.n, 1.0 / L, (int)pl.perm, (double)kDepOpScale / qscale, rec);
+    const double unscale = qscale / ((double)kDepOpScale * (double)kDepOpScale);
     switch (mfma_cs_tiles(g.n)) {
-    case 1: launch_dep_mt<1>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
-    case 2: launch_dep_mt<2>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
-    case 3: launch_dep_mt<3>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
-    case 4: launch_dep_mt<4>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
-    case 5: launch_dep_mt<5>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
-    case 6: launch_dep_mt<6>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
-    case 7: launch_dep_mt<7>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
-    case 8: launch_dep_mt<8>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
-    default: launch_dep_mt<9>(s, pos_turns, q, N, g, pl, 1.0, qscale, part); break;
+    case 1: launch_dep_mt<1>(s, rec, N, g, pl, unscale, part); break;
+    case 2: launch_dep_mt<2>(s, rec, N, g, pl, unscale, part); break;
+    case 3: launch_dep_mt<3>(s, rec, N, g, pl, unscale, part); break;
+    case 4: launch_dep_mt<4>(s, rec, N, g, pl, unscale, part); break;
+    case 5: launch_dep_mt<5>(s, rec, N, g, pl, unscale, part); break;
+    case 6: launch_dep_mt<6>(s, rec, N, g, pl, unscale, part); break;
+    case 7: launch_dep_mt<7>(s, rec, N, g, pl, unscale, part); break;
+    case 8: launch_dep_mt<8>(s, rec, N, g, pl, unscale, part); break;
+    default: launch_dep_mt<9>(s, rec, N, g, pl, unscale, part); break;
     }
-    return hipGetLastError();
-}
-
-// positions in turns: t = frac(x / L), [3][N]
-__global__ void __launch_bounds__(256)
-k_turns(const double *__restrict__ pos, int64_t n3, double invL, double *__restrict__ out)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n3) out[i] = frac(pos[i] * invL);
-}
-
-hipError_t launch_turns(hipStream_t s, const double *pos, int64_t N, double L, double *out)
-{
-    const int64_t blocks = (3 * N + 255) / 256;
-    hipLaunchKernelGGL(k_turns, dim3((unsigned)blocks), dim3(256), 0, s, pos, 3 * N, 1.0 / L, out);
     return hipGetLastError();
 }
 

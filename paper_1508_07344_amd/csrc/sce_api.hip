@@ -51,7 +51,7 @@ struct sce_ctx_s {
     double *Stab = nullptr, *Gtab = nullptr, *Ktab = nullptr;
     double2 *rho = nullptr, *psi = nullptr;
     void *ftab = nullptr, *psi0 = nullptr;
-    // split-precision path: positions in turns, packed force fragments, scale scratch
+    // split-precision path: particle records, packed force fragments, row scales
     double *turns = nullptr;
     size_t turns_bytes = 0;
     void *wf = nullptr;
@@ -311,7 +311,7 @@ sce_status run_deposit_split(sce_ctx c)
     const Geom &g = c->g;
     const sce::MfmaDepositPlan pl = sce::plan_deposit_mfma(g, c->N);
     void *tp = c->turns;
-    sce_status st = ensure_bytes(c, tp, c->turns_bytes, (size_t)3 * c->N * sizeof(double));
+    sce_status st = ensure_bytes(c, tp, c->turns_bytes, sce::deposit_mfma_rec_bytes(c->N, g.n));
     c->turns = (double *)tp;
     if (st) return st;
     size_t pb = c->part_bytes;
@@ -320,14 +320,14 @@ sce_status run_deposit_split(sce_ctx c)
     c->part = (double *)pp;
     c->part_bytes = pb;
     if (st) return st;
-    HIPCHK(c, sce::launch_turns(c->stream, c->pos, c->N, c->L, c->turns));
     EventPair ep{nullptr, nullptr};
     if (c->timing) {
         ep.a = take_event(c);
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
-    HIPCHK(c, sce::launch_deposit_mfma(c->stream, c->turns, c->q, c->N, g, pl, c->qscale, c->part));
+    HIPCHK(c, sce::launch_deposit_mfma(c->stream, c->pos, c->q, c->N, g, c->L, pl, c->qscale,
+                                       (float *)c->turns, c->part));
     if (c->timing && ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_dep.push_back(ep);

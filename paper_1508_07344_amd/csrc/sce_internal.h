@@ -103,13 +103,13 @@ struct MfmaDepositPlan {
     int64_t perm;       // half width h of the Feistel visiting order (2^(2h) >= N)
 };
 MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N);
-// positions in turns t = frac(x / L), [3][N]
-hipError_t launch_turns(hipStream_t s, const double *pos, int64_t N, double L, double *out);
-// Deposit partial sums (same layout as launch_deposit) from positions in turns;
-// charges are scaled by 1/qscale inside and the partials by qscale.
-hipError_t launch_deposit_mfma(hipStream_t s, const double *pos_turns, const double *q, int64_t N,
-                               const Geom &g, const MfmaDepositPlan &pl, double qscale,
-                               double *part);
+// Deposit partial sums (same layout as launch_deposit).  rec: scratch of
+// deposit_mfma_rec_bytes(N) for the per-particle records in visiting order;
+// charges enter scaled by 1/qscale and the partials leave scaled back.
+size_t deposit_mfma_rec_bytes(int64_t N, int n);
+hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q, int64_t N,
+                               const Geom &g, double L, const MfmaDepositPlan &pl, double qscale,
+                               float *rec, double *part);
 // Pack the FP32 force table into FP16 hi/lo matrix-core fragments, each row
 // scaled by its power-of-two scale rowscale[r] (R floats, written here).
 size_t force_pack_bytes(const Geom &g);
