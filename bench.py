@@ -43,8 +43,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "split_f16"])
-    ap.add_argument("--also", default="fp64", help="comma list of extra precisions to time")
+    ap.add_argument("--precision", default="split_f16", choices=["fp64", "fp32", "split_f16"])
+    ap.add_argument("--also", default="fp64,fp32", help="comma list of extra precisions to time")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=16384,
                     help="particles in the oracle's timed sample (all modes)")
@@ -89,18 +89,43 @@ def time_path(sce, p, precision, steps, warmup):
     return out
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of a matrix-core kernel from the committed rocprofv3
+    summary, or None if the kernel source changed since it was measured."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1508_07344_amd", "csrc", "kernels_mfma.hip")
+    summ = os.path.join(ROOT, "profiles", "traffic_cold_lattice_1M_n32.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        txt = open(summ).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic kernel=%s fetch_bytes=(\S+) write_bytes=(\S+) source_sha256_16=(\w+)" % kernel, txt)
+    if not m or m.group(3) != sha:
+        return None
+    return float(m.group(1)) + float(m.group(2))
+
+
 def roofline(r, N):
+    """Roofline of the dominant (longer) of the two particle x mode kernels.
+    achieved = algorithmic flops per launch / average launch time, with the
+    algorithmic count of complex multiply-adds: 8 flops per pair for the
+    deposit, 16 for the force."""
     pairs = N * r["modes_half"]
-    t = r["force_ms_avg"] * 1e-3
-    achieved = FLOPS_PER_PAIR["force"] * pairs / t / 1e12
-    peak = PEAK_TFLOPS[r["precision"]]
-    dep = FLOPS_PER_PAIR["deposit"] * pairs / (r["deposit_ms_avg"] * 1e-3) / 1e12
     mf = r["precision"] == "split_f16"
-    return {"bound": BOUND[r["precision"]], "kernel": "k_force_mfma" if mf else "k_force",
-            "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "deposit_kernel": {"kernel": "k_deposit_mfma" if mf else "k_deposit",
-                               "achieved": round(dep, 3), "frac": round(dep / peak, 4)}}
+    peak = PEAK_TFLOPS[r["precision"]]
+    kern = {"deposit": ("k_deposit_mfma" if mf else "k_deposit", r["deposit_ms_avg"]),
+            "force": ("k_force_mfma" if mf else "k_force", r["force_ms_avg"])}
+    rates = {k: FLOPS_PER_PAIR[k] * pairs / (t * 1e-3) / 1e12 for k, (_, t) in kern.items()}
+    dom = max(kern, key=lambda k: kern[k][1])
+    other = "force" if dom == "deposit" else "deposit"
+    traffic = measured_traffic(kern[dom][0]) if mf else None
+    return {"bound": BOUND[r["precision"]], "kernel": kern[dom][0],
+            "achieved": round(rates[dom], 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(rates[dom] / peak, 4), "traffic": traffic,
+            "other_kernel": {"kernel": kern[other][0], "achieved": round(rates[other], 3),
+                             "frac": round(rates[other] / peak, 4)}}
 
 
 def cpu_baseline(p, sample):
