@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--precision", default="split_f16", choices=["fp64", "fp32", "split_f16"])
     ap.add_argument("--also", default="fp64,fp32", help="comma list of extra precisions to time")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=16384,
+    ap.add_argument("--cpu-sample", type=int, default=49152,
                     help="particles in the oracle's timed sample (all modes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device-to-device copy of this many MiB (five times), "

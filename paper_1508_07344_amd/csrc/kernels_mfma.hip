@@ -13,8 +13,8 @@
 // Every FP32 operand x is carried as two FP16 values hi = fp16(x),
 // lo = fp16(x - hi); a product uses hi*hi + hi*lo + lo*hi (the lo*lo term,
 // ~2^-22 relative, is dropped), accumulated in FP32 by the matrix core.
-// Operands are scaled to magnitude <= 1 first (charges by 1/max|q|, the
-// force table by 1/max|entry|) so FP16's range is never exceeded.
+// Operands are scaled to magnitude <= 1 first (charges by 1/max|q|, each
+// force-table row by a power of two) so FP16's range is never exceeded.
 //
 // Fragment layout of v_mfma_f32_16x16x32_f16 (lane l, element i):
 //   A[m][k]: m = l % 16, k = 8 (l / 16) + i     (8 halves)
