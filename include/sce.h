@@ -178,6 +178,85 @@ const char *sce_status_string(sce_status s);
 /* Last error message of this context ("" if none). */
 const char *sce_last_error(sce_ctx ctx);
 
+/* ------------------------------------------------------------------ serving
+ * Batched serving of many independent small simulations (each one the model
+ * above, with its own L, n_max, shape and particles) on one GPU.  Their state
+ * stays resident in one device arena; each sce_server_tick advances every
+ * resident request by one leapfrog pass with one launch per phase (deposit,
+ * solve, force with kick and drift, diagnostics) for all of them together.
+ * A request of S steps takes S + 1 passes: the kick-drift-kick step of
+ * Section 4 with the kicks of consecutive steps merged (h/2 on the first and
+ * last pass, h in between), which gives the same states as S calls of the
+ * single-simulation step.  Requests are admitted first-in first-out while
+ * their device footprint fits the arena and a slot is free.
+ * A server is not thread-safe; its calls synchronise its stream. */
+typedef struct sce_server_s *sce_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;  /* device arena for resident requests; 0 = 4 GiB */
+    int32_t precision;        /* SCE_PREC_FP32 or SCE_PREC_FP64 */
+    int32_t max_active;       /* resident requests at most; 0 = 4096 */
+    void *hip_stream;         /* hipStream_t, or NULL for a server-owned stream */
+} sce_server_opts;
+
+typedef struct {
+    double L, a, eps0, dt;    /* box side (> 0), shape width (>= 0), eps0 (> 0), step (finite) */
+    int32_t n_max;            /* 1 .. 16 */
+    int32_t shape_kind;       /* sce_shape_kind */
+    int64_t N;                /* particles, >= 1 */
+    int64_t n_steps;          /* >= 0 */
+    const double *x, *v;      /* host [3][N]; positions outside [0, L) are wrapped by the first drift */
+    const double *q, *m;      /* host [N]; m > 0 */
+} sce_request;
+
+typedef struct {
+    int64_t ticks;            /* ticks that advanced at least one request */
+    int64_t request_steps;    /* passes completed, summed over requests */
+    int64_t requests_done;
+    int64_t active, queued;   /* now */
+    double busy_s;            /* wall time inside those ticks */
+    double pairs;             /* sum over ticks of sum over resident requests of N |H| */
+    double p50_step_s, p99_step_s, max_step_s;  /* per request-pass latency: the wall time of the
+                                                   tick that carried it (admission, launches,
+                                                   retirement included) */
+    double p50_wait_s, p99_wait_s;              /* admission wait: submit to the start of the
+                                                   first tick that carried the request */
+    double hbm_used_bytes, hbm_peak_bytes;      /* arena bytes held by resident requests */
+} sce_server_report;
+
+/* Create a server on the current HIP device.  opts may be NULL (defaults).
+ * Errors: SCE_EINVAL (out == NULL, max_active < 0), SCE_ENOTSUP (precision
+ * other than FP32 or FP64), SCE_ENOMEM (arena allocation failed). */
+sce_status sce_server_create(const sce_server_opts *opts, sce_server *out);
+
+/* Queue a request; its arrays are copied before returning.  *id (> 0) names it.
+ * Errors: SCE_EINVAL for invalid fields, or if its footprint exceeds the whole
+ * arena (it could never be admitted). */
+sce_status sce_server_submit(sce_server s, const sce_request *req, uint64_t *id);
+
+/* Admit what fits, then run one pass of every resident request and retire the
+ * finished ones (their results move to host memory).  n_active and n_queued
+ * (may be NULL) receive the counts after the tick. */
+sce_status sce_server_tick(sce_server s, int32_t *n_active, int32_t *n_queued);
+
+/* Ids of requests finished since the last poll, oldest first, at most max. */
+sce_status sce_server_poll(sce_server s, uint64_t *done_ids, int32_t max, int32_t *n_done);
+
+/* Result of a finished request, then forgotten: x, v, F host [3][N] at the
+ * end (F at the final positions), diagnostics at the start (first) and the
+ * end (last).  Any output may be NULL.  SCE_EINVAL if id is not finished or
+ * was already fetched. */
+sce_status sce_server_result(sce_server s, uint64_t id, double *x, double *v, double *F,
+                             sce_diag *first, sce_diag *last);
+
+sce_status sce_server_stats(sce_server s, sce_server_report *out);
+
+/* Last error message of this server ("" if none). */
+const char *sce_server_last_error(sce_server s);
+
+/* Release the server, its arena and all unfetched results.  NULL is ignored. */
+void sce_server_destroy(sce_server s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,9 +7,9 @@ device memory and streams.  There is no CPU fallback: if the library is not
 built, or no GPU is visible, calls raise.
 """
 from .sce import (SCE_OK, SCE_EINVAL, SCE_ENOMEM, SCE_EDEVICE, SCE_ESTATE, SCE_ENOTSUP,
-                  SCE_EUNSTABLE, PREC, SCHEME, SHAPE, Diag, SceError, Context, load_library,
+                  SCE_EUNSTABLE, PREC, SCHEME, SHAPE, Diag, SceError, Context, Server, load_library,
                   library_path, exported_symbols)
 
 __all__ = ["SCE_OK", "SCE_EINVAL", "SCE_ENOMEM", "SCE_EDEVICE", "SCE_ESTATE", "SCE_ENOTSUP",
-           "SCE_EUNSTABLE", "PREC", "SCHEME", "SHAPE", "Diag", "SceError", "Context",
+           "SCE_EUNSTABLE", "PREC", "SCHEME", "SHAPE", "Diag", "SceError", "Context", "Server",
            "load_library", "library_path", "exported_symbols"]

@@ -38,6 +38,29 @@ class _Diag(ctypes.Structure):
                 ("rho_abs_max", ctypes.c_double)]
 
 
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("precision", ctypes.c_int32),
+                ("max_active", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("a", ctypes.c_double), ("eps0", ctypes.c_double),
+                ("dt", ctypes.c_double), ("n_max", ctypes.c_int32), ("shape_kind", ctypes.c_int32),
+                ("N", ctypes.c_int64), ("n_steps", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("v", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("m", ctypes.c_void_p)]
+
+
+class _ServerReport(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_int64), ("request_steps", ctypes.c_int64),
+                ("requests_done", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("busy_s", ctypes.c_double), ("pairs", ctypes.c_double),
+                ("p50_step_s", ctypes.c_double), ("p99_step_s", ctypes.c_double),
+                ("max_step_s", ctypes.c_double), ("p50_wait_s", ctypes.c_double),
+                ("p99_wait_s", ctypes.c_double), ("hbm_used_bytes", ctypes.c_double),
+                ("hbm_peak_bytes", ctypes.c_double)]
+
+
 @dataclasses.dataclass
 class Diag:
     step: int
@@ -94,6 +117,15 @@ def load_library():
         "sce_destroy": ([P], None),
         "sce_status_string": ([i32], ctypes.c_char_p),
         "sce_last_error": ([P], ctypes.c_char_p),
+        "sce_server_create": ([ctypes.POINTER(_ServerOpts), ctypes.POINTER(P)], i32),
+        "sce_server_submit": ([P, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)], i32),
+        "sce_server_tick": ([P, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "sce_server_poll": ([P, P, i32, ctypes.POINTER(i32)], i32),
+        "sce_server_result": ([P, ctypes.c_uint64, P, P, P, ctypes.POINTER(_Diag),
+                               ctypes.POINTER(_Diag)], i32),
+        "sce_server_stats": ([P, ctypes.POINTER(_ServerReport)], i32),
+        "sce_server_last_error": ([P], ctypes.c_char_p),
+        "sce_server_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -294,3 +326,87 @@ class Context:
             c.sce_set_particles(p.positions(), p.velocities(), np.ascontiguousarray(p.q),
                                 np.ascontiguousarray(p.m))
         return c
+
+
+def _diag(d: _Diag) -> Diag:
+    return Diag(d.step, d.time, d.kinetic, d.field, d.field_self, d.interaction, d.total,
+                np.array(list(d.momentum)), d.momentum_abs_sum, d.rho_abs_max)
+
+
+class Server:
+    """Batched server of independent simulations (``sce_server``)."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, precision: str = "fp32", max_active: int = 0):
+        lib = load_library()
+        self._lib = lib
+        o = _ServerOpts(hbm_budget_bytes, PREC[precision], max_active, None)
+        h = ctypes.c_void_p()
+        st = lib.sce_server_create(ctypes.byref(o), ctypes.byref(h))
+        if st != SCE_OK:
+            raise SceError(st, lib.sce_status_string(st).decode())
+        self._h = h
+        self._sizes = {}
+
+    def _chk(self, st: int, what: str):
+        if st != SCE_OK:
+            msg = self._lib.sce_server_last_error(self._h).decode()
+            raise SceError(st, f"{what}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sce_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def sce_server_submit(self, p, n_steps: int | None = None) -> int:
+        """Queue a ``workloads.Particles`` record (its dt, n_steps unless given)."""
+        x = np.ascontiguousarray(p.positions(), dtype=np.float64)
+        v = np.ascontiguousarray(p.velocities(), dtype=np.float64)
+        q = np.ascontiguousarray(p.q, dtype=np.float64)
+        m = np.ascontiguousarray(p.m, dtype=np.float64)
+        steps = p.n_steps if n_steps is None else n_steps
+        r = _Request(p.L, p.a, p.eps0, p.dt, p.n_max, SHAPE[p.shape], p.N, steps,
+                     _host(x), _host(v), _host(q), _host(m))
+        rid = ctypes.c_uint64()
+        self._chk(self._lib.sce_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "submit")
+        self._sizes[rid.value] = p.N
+        return rid.value
+
+    def sce_server_tick(self):
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        self._chk(self._lib.sce_server_tick(self._h, ctypes.byref(a), ctypes.byref(q)), "tick")
+        return a.value, q.value
+
+    def sce_server_poll(self, max_ids: int = 4096) -> list:
+        ids = (ctypes.c_uint64 * max(max_ids, 1))()
+        n = ctypes.c_int32()
+        self._chk(self._lib.sce_server_poll(self._h, ids, max_ids, ctypes.byref(n)), "poll")
+        return [ids[i] for i in range(n.value)]
+
+    def sce_server_result(self, rid: int):
+        """(x, v, F, first Diag, last Diag) of a finished request."""
+        if rid not in self._sizes:
+            raise SceError(SCE_EINVAL, f"result: unknown or already fetched request {rid}")
+        N = self._sizes[rid]
+        x, v, F = (np.empty((3, N)) for _ in range(3))
+        d0, d1 = _Diag(), _Diag()
+        self._chk(self._lib.sce_server_result(self._h, rid, _host(x), _host(v), _host(F),
+                                              ctypes.byref(d0), ctypes.byref(d1)), "result")
+        del self._sizes[rid]
+        return x, v, F, _diag(d0), _diag(d1)
+
+    def sce_server_stats(self) -> dict:
+        r = _ServerReport()
+        self._chk(self._lib.sce_server_stats(self._h, ctypes.byref(r)), "stats")
+        return {name: getattr(r, name) for name, _ in r._fields_}

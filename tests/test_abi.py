@@ -24,7 +24,9 @@ def test_header_declares_the_api():
                      "sce_mode_count", "sce_modes", "sce_deposit", "sce_psi", "sce_force",
                      "sce_step", "sce_diagnostics", "sce_get_state", "sce_set_state", "sce_sync",
                      "sce_timing_enable", "sce_timing_read", "sce_destroy", "sce_status_string",
-                     "sce_last_error"):
+                     "sce_last_error", "sce_server_create", "sce_server_submit", "sce_server_tick",
+                     "sce_server_poll", "sce_server_result", "sce_server_stats",
+                     "sce_server_last_error", "sce_server_destroy"):
         assert required in names
 
 
@@ -64,3 +66,23 @@ def test_status_strings():
     lib = _lib()
     for s in range(-6, 1):
         assert lib.sce_status_string(s).decode()
+
+
+def test_server_arguments_are_rejected_on_host():
+    from paper_1508_07344_amd.sce import _ServerOpts
+    lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.sce_server_create(None, None) == sce.SCE_EINVAL
+    for prec, max_active, want in [(sce.PREC["split_f16"], 0, sce.SCE_ENOTSUP), (7, 0, sce.SCE_ENOTSUP),
+                                   (sce.PREC["fp32"], -1, sce.SCE_EINVAL)]:
+        o = _ServerOpts(0, prec, max_active, None)
+        assert lib.sce_server_create(ctypes.byref(o), ctypes.byref(h)) == want
+        assert not h.value
+    n = ctypes.c_int32()
+    assert lib.sce_server_tick(None, None, None) == sce.SCE_EINVAL
+    assert lib.sce_server_submit(None, None, None) == sce.SCE_EINVAL
+    assert lib.sce_server_poll(None, None, 0, ctypes.byref(n)) == sce.SCE_EINVAL
+    assert lib.sce_server_result(None, 1, None, None, None, None, None) == sce.SCE_EINVAL
+    assert lib.sce_server_stats(None, None) == sce.SCE_EINVAL
+    assert lib.sce_server_last_error(None).decode()
+    lib.sce_server_destroy(None)  # no-op
