@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=49152,
                     help="particles in the oracle's timed sample (all modes)")
+    ap.add_argument("--serve-requests", type=int, default=1024,
+                    help="requests of the serving workload (0 = skip the serving run)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="offered load as a fraction of the measured saturated capacity")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device-to-device copy of this many MiB (five times), "
                          "the reference kernel for scaling the FETCH_SIZE/WRITE_SIZE counters")
@@ -128,6 +132,92 @@ def roofline(r, N):
                              "frac": round(rates[other] / peak, 4)}}
 
 
+def _drive(srv, reqs, t_arrive):
+    """Submit each request at its arrival time (seconds from now) and tick until
+    every request has finished.  Returns wall seconds and the server's ids."""
+    order = sorted(range(len(reqs)), key=lambda i: t_arrive[i])
+    ids = {}
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        now = time.perf_counter() - t0
+        while k < len(order) and t_arrive[order[k]] <= now:
+            i = order[k]
+            ids[srv.sce_server_submit(reqs[i].particles)] = i
+            k += 1
+        na, nq = srv.sce_server_tick()
+        if na == 0 and nq == 0:
+            if k == len(order):
+                break
+            time.sleep(max(0.0, min(1e-3, t_arrive[order[k]] - (time.perf_counter() - t0))))
+    return time.perf_counter() - t0, ids
+
+
+def serving(sce, n_requests, load):
+    """Serving workload: independent requests (N log-uniform in [2, 8192], n_max
+    in {4, 8, 16}, steps log-uniform in [100, 10^4]) with Poisson arrivals at
+    ``load`` x the saturated capacity measured first on the same mix."""
+    import numpy as np
+    import workloads
+
+    def half(n):
+        return ((2 * n + 1) ** 3 - 1) // 2
+
+    # saturated capacity: 256 requests of the same mix (steps / 10) submitted at once
+    cal = workloads.serving_requests(n_requests=256, steps_range=(10, 1000), salt=1)
+    with sce.Server(hbm_budget_bytes=16 << 30, precision="fp32") as srv:
+        _drive(srv, cal, [0.0] * len(cal))
+        st = srv.sce_server_stats()
+    capacity = st["pairs"] / st["busy_s"]
+
+    # unit-rate Poisson arrivals, rescaled to ``rate`` (the draws do not depend on the rate)
+    reqs = workloads.serving_requests(n_requests=n_requests, rate_per_s=1.0)
+    work = np.array([r.particles.N * half(r.particles.n_max) * (r.particles.n_steps + 1) for r in reqs],
+                    dtype=np.float64)
+    rate = load * capacity / float(np.mean(work))
+    t_arrive = [r.arrival_s / rate for r in reqs]
+    with sce.Server(hbm_budget_bytes=16 << 30, precision="fp32") as srv:
+        wall, ids = _drive(srv, reqs, t_arrive)
+        st = srv.sce_server_stats()
+        done = srv.sce_server_poll(len(reqs) + 1)
+        drift, errs = [], []
+        sample = set(done[:: max(1, len(done) // 16)])
+        for rid in done:
+            x, v, F, d0, d1 = srv.sce_server_result(rid)
+            drift.append(abs(d1.total - d0.total) / abs(d0.total))
+            if rid in sample:
+                p = reqs[ids[rid]].particles
+                with sce.Context(p.L, p.n_max, p.shape, p.a) as c:
+                    c.sce_set_options(p.eps0, "fp64", "kdk")
+                    c.sce_set_particles(np.ascontiguousarray(x), np.ascontiguousarray(v),
+                                        np.ascontiguousarray(p.q), np.ascontiguousarray(p.m))
+                    Fr = c.sce_force()
+                errs.append(float(np.max(np.linalg.norm(F - Fr, axis=0)) /
+                                  max(np.max(np.linalg.norm(Fr, axis=0)), 1e-300)))
+    return {
+        "workload": f"{n_requests} requests, N log-uniform [2, 8192], n_max in {{4, 8, 16}}, "
+                    "steps log-uniform [100, 1e4], Gaussian a = 0.05, dt = 1e-3, Poisson arrivals",
+        "precision": "fp32",
+        "offered_load": load,
+        "capacity_pairs_per_s": capacity,
+        "arrival_rate_per_s": rate,
+        "wall_s": wall,
+        "pairs_per_s": st["pairs"] / wall,
+        "request_steps_per_s": st["request_steps"] / wall,
+        "p50_step_ms": 1e3 * st["p50_step_s"],
+        "p99_step_ms": 1e3 * st["p99_step_s"],
+        "max_step_ms": 1e3 * st["max_step_s"],
+        "p50_wait_ms": 1e3 * st["p50_wait_s"],
+        "p99_wait_ms": 1e3 * st["p99_wait_s"],
+        "requests": int(st["requests_done"]),
+        "hbm_peak_bytes": st["hbm_peak_bytes"],
+        "energy_drift_rel_p50": float(np.median(drift)),
+        "energy_drift_rel_max": float(np.max(drift)),
+        "e_F_vs_fp64_max": float(np.max(errs)),
+        "e_F_sampled_requests": len(errs),
+    }
+
+
 def cpu_baseline(p, sample):
     import numpy as np
     import oracle
@@ -193,6 +283,8 @@ def main():
         "detail": {k: v for k, v in main_r.items() if k not in ("precision",)},
         "variants": variants,
     }
+    if a.serve_requests:
+        line["serving"] = serving(sce, a.serve_requests, a.serve_load)
     if a.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, a.cpu_sample)
     print(json.dumps(line), flush=True)
