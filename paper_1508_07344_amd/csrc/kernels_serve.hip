@@ -72,7 +72,9 @@ __device__ void dep_body(const ReqDesc &d, int idx, char *__restrict__ arena, ch
     const int tile = idx / d.segs, seg = idx - tile * d.segs;
     const double *__restrict__ pos = reinterpret_cast<const double *>(arena + d.o_pos);
     const double *__restrict__ q = reinterpret_cast<const double *>(arena + d.o_q);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wave index is wave-uniform; readfirstlane lets the compiler keep it
+    // (and the particle loop below) in scalar registers
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = tile * 64 + lane;
     int nx, ny;
     row_nxny(r < d.R ? r : 0, d.n, nx, ny);
@@ -290,11 +292,13 @@ k_serve_reduce(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
 // wave 0 applies the pass's kick and drift and writes the item's diagnostics
 // partials (a fixed shuffle tree, so repeated runs give identical bits).
 template <typename T, int NZ>
-__device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena, double *shd)
+__device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
+                         const char *__restrict__ tabs, double *shd)
 {
     constexpr int NK = NZ - 1;
     const int64_t N = d.N;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // wave-uniform row range: scalar loads of the force table
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t j = (int64_t)idx * 64 + lane;
     const int64_t jc = j < N ? j : N - 1;
     double *pos = reinterpret_cast<double *>(arena + d.o_pos);
@@ -323,8 +327,8 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena, do
     double eyc, eys;
     cis_turns(ty, eyc, eys);
 
-    const T *__restrict__ ftab = reinterpret_cast<const T *>(arena + d.o_ftab);
-    const T *__restrict__ psi0 = reinterpret_cast<const T *>(arena + d.o_psi0);
+    const T *__restrict__ ftab = reinterpret_cast<const T *>(tabs + d.o_ftab);
+    const T *__restrict__ psi0 = reinterpret_cast<const T *>(tabs + d.o_psi0);
     const int n = d.n, R = d.R;
     const int r0 = (R * w) / 4, r1 = (R * (w + 1)) / 4;
     double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
@@ -443,43 +447,51 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena, do
     }
 }
 
+// tabs: the arena again, read-only here (force tables only; particle state is
+// read and written through arena), so that the wave-uniform table rows can be
+// fetched with scalar loads.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_serve_force(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
-              const ServeItem *__restrict__ items)
+              const char *__restrict__ tabs, const ServeItem *__restrict__ items)
 {
     __shared__ double shd[3 * 64 * 4];
     const ServeItem it = items[blockIdx.x];
     const ReqDesc &d = desc[it.slot];
     if (d.nzs == 5)
-        frc_body<T, 5>(d, it.idx, arena, shd);
+        frc_body<T, 5>(d, it.idx, arena, tabs, shd);
     else if (d.nzs == 9)
-        frc_body<T, 9>(d, it.idx, arena, shd);
+        frc_body<T, 9>(d, it.idx, arena, tabs, shd);
     else
-        frc_body<T, 17>(d, it.idx, arena, shd);
+        frc_body<T, 17>(d, it.idx, arena, tabs, shd);
 }
 
 // ------------------------------------------------------------------ diagnostics + pass count
-// One thread per resident request: sums the item partials in item order,
-// records the first and last pass's diagnostics, and counts the pass.
+// One wave per resident request: lane l sums the item partials l, l+64, ...
+// in order, a fixed shuffle tree adds the lanes; records the first and last
+// pass's diagnostics and counts the pass.
 __global__ void __launch_bounds__(64)
-k_serve_diag(ReqDesc *__restrict__ desc, char *__restrict__ arena, const int *__restrict__ slots,
-             int nslots)
+k_serve_diag(ReqDesc *__restrict__ desc, char *__restrict__ arena, const int *__restrict__ slots)
 {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i >= nslots) return;
-    ReqDesc &d = desc[slots[i]];
+    const int lane = threadIdx.x;
+    ReqDesc &d = desc[slots[blockIdx.x]];
     const double *fpart = reinterpret_cast<const double *>(arena + d.o_fpart);
     const double *rpart = reinterpret_cast<const double *>(arena + d.o_rpart);
     double s[kServeFDiag];
     for (int c = 0; c < kServeFDiag; ++c) s[c] = 0.0;
-    for (int b = 0; b < d.fblocks; ++b)
+    for (int b = lane; b < d.fblocks; b += 64)
         for (int c = 0; c < kServeFDiag; ++c) s[c] += fpart[b * kServeFDiag + c];
     double W = 0.0, mx = 0.0;
-    for (int b = 0; b < d.rblocks; ++b) {
+    for (int b = lane; b < d.rblocks; b += 64) {
         W += rpart[2 * b];
         mx = fmax(mx, rpart[2 * b + 1]);
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        for (int c = 0; c < kServeFDiag; ++c) s[c] += __shfl_xor(s[c], o, 64);
+        W += __shfl_xor(W, o, 64);
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    if (lane != 0) return;
     double *diag = reinterpret_cast<double *>(arena + d.o_diag);
     const int64_t p = d.pass;
     if (p == 0) {
@@ -504,10 +516,11 @@ hipError_t tick(hipStream_t s, const ReqDesc *desc, char *arena, const ServeItem
     if (nred > 0)
         hipLaunchKernelGGL(k_serve_reduce<T>, dim3(nred), dim3(256), 0, s, desc, arena, red);
     if (nfrc > 0)
-        hipLaunchKernelGGL(k_serve_force<T>, dim3(nfrc), dim3(256), 0, s, desc, arena, frc);
+        hipLaunchKernelGGL(k_serve_force<T>, dim3(nfrc), dim3(256), 0, s, desc, arena,
+                           (const char *)arena, frc);
     if (nslots > 0)
-        hipLaunchKernelGGL(k_serve_diag, dim3((nslots + 63) / 64), dim3(64), 0, s,
-                           const_cast<ReqDesc *>(desc), arena, slots, nslots);
+        hipLaunchKernelGGL(k_serve_diag, dim3(nslots), dim3(64), 0, s, const_cast<ReqDesc *>(desc),
+                           arena, slots);
     return hipGetLastError();
 }
 

@@ -302,15 +302,22 @@ sce_status build_lists(sce_server s)
     return SCE_OK;
 }
 
-sce_status retire(sce_server s)
+// Requests whose last pass runs in this tick: enqueue the copies of their
+// final state behind the tick's kernels (one synchronisation covers both).
+sce_status stage_finishing(sce_server s, std::vector<Request *> &fin)
 {
-    std::vector<Request *> fin;
+    fin.clear();
     for (auto &r : s->active)
-        if (r->pass > r->d.n_steps) fin.push_back(r.get());
+        if (r->pass == r->d.n_steps) fin.push_back(r.get());
     if (fin.empty()) return SCE_OK;
     size_t tot = 0;
     for (Request *r : fin) tot += 9 * (size_t)r->d.N + sce::kServeDiag;
     SHIP(s, s->stage.reserve(tot));
+    return SCE_OK;
+}
+
+sce_status copy_finishing(sce_server s, const std::vector<Request *> &fin)
+{
     size_t off = 0;
     for (Request *r : fin) {
         const ReqDesc &d = s->desc.host[r->slot];
@@ -323,8 +330,15 @@ sce_status retire(sce_server s)
                                hipMemcpyDeviceToHost, s->stream));
         off += 9 * N + sce::kServeDiag;
     }
-    SHIP(s, hipStreamSynchronize(s->stream));
-    off = 0;
+    return SCE_OK;
+}
+
+// After the tick's synchronisation: move the staged results to host storage
+// and release the finished requests' arena blocks and slots.
+void retire(sce_server s, const std::vector<Request *> &fin)
+{
+    if (fin.empty()) return;
+    size_t off = 0;
     for (Request *r : fin) {
         const size_t N = (size_t)r->d.N;
         const double *h = s->stage.host + off;
@@ -347,7 +361,6 @@ sce_status retire(sce_server s)
                                    [](const std::unique_ptr<Request> &r) { return r->pass > r->d.n_steps; }),
                     s->active.end());
     s->dirty = true;
-    return SCE_OK;
 }
 
 void fill_diag(sce_diag *o, const double *d, double self_w, int64_t step, double dt)
@@ -480,18 +493,28 @@ sce_status sce_server_tick(sce_server s, int32_t *n_active, int32_t *n_queued)
         if (st != SCE_OK) return st;
     }
     if (!s->active.empty()) {
+        std::vector<Request *> fin;
+        st = stage_finishing(s, fin);
+        if (st != SCE_OK) return st;
         SHIP(s, sce::launch_serve_tick(s->stream, s->elem, s->desc.dev, s->arena, s->dep.dev, s->ndep,
                                        s->red.dev, s->nred, s->frc.dev, s->nfrc, s->slots.dev,
                                        s->nslots));
+        st = copy_finishing(s, fin);
+        if (st != SCE_OK) return st;
         SHIP(s, hipStreamSynchronize(s->stream));
         const int na = (int)s->active.size();
         double pr = 0.0;
         for (auto &r : s->active) {
             ++r->pass;
             pr += (double)r->d.N * (double)half_modes(r->d.n);
+            if (!r->x.empty()) {  // uploaded at admission; the copies have completed
+                std::vector<double>().swap(r->x);
+                std::vector<double>().swap(r->v);
+                std::vector<double>().swap(r->q);
+                std::vector<double>().swap(r->m);
+            }
         }
-        st = retire(s);
-        if (st != SCE_OK) return st;
+        retire(s, fin);
         const double dt = now_s() - t0;
         s->tick_lat.emplace_back(dt, na);
         ++s->ticks;
