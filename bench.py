@@ -52,6 +52,10 @@ def parse():
                     help="requests of the serving workload (0 = skip the serving run)")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load as a fraction of the measured saturated capacity")
+    ap.add_argument("--study", default="", choices=["", "longrun", "dispersion", "h2"],
+                    help="run one validation study instead of the throughput benchmark")
+    ap.add_argument("--long-steps", type=int, default=100000,
+                    help="steps of the long-run conservation study")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device-to-device copy of this many MiB (five times), "
                          "the reference kernel for scaling the FETCH_SIZE/WRITE_SIZE counters")
@@ -218,6 +222,148 @@ def serving(sce, n_requests, load):
     }
 
 
+# ---------------------------------------------------------------- studies
+def _mode_index(n, m):
+    """Canonical index of mode (m, 0, 0): the n_x = 0 block (n + n M modes), the
+    n_x = 1 .. m-1 blocks (M^2 each), then n_y = -n .. -1 rows of n_x = m, then n_z = 0."""
+    M = 2 * n + 1
+    return n + n * M + (m - 1) * M * M + n * M + n
+
+
+def _fit_omega(series, t, w_guess):
+    """Least-squares frequency of a + b cos(w t) + c sin(w t): a grid over
+    [0.7, 1.3] w_guess, then a bounded scalar minimisation around the best point."""
+    import numpy as np
+    from scipy.optimize import minimize_scalar
+
+    def resid(w):
+        A = np.stack([np.cos(w * t), np.sin(w * t), np.ones_like(t)], axis=1)
+        coef, *_ = np.linalg.lstsq(A, series, rcond=None)
+        return float(np.sum((A @ coef - series) ** 2))
+
+    ws = np.linspace(0.7 * w_guess, 1.3 * w_guess, 1201)
+    i = int(np.argmin([resid(w) for w in ws]))
+    lo, hi = ws[max(i - 1, 0)], ws[min(i + 1, len(ws) - 1)]
+    return float(minimize_scalar(resid, bounds=(lo, hi), method="bounded",
+                                 options={"xatol": 1e-9 * w_guess}).x)
+
+
+def study_dispersion(sce):
+    """Cold-plasma oscillation of mode (m, 0, 0) on the 2^20-particle lattice
+    against the discrete dispersion relation (Section 5),
+    w = (2/h) asin(w_p h S(k)/2), for several m and h, and the growth factor of
+    the unstable regime w_p h S / 2 > 1, where |lambda| + 1/|lambda| = (w_p h S)^2 - 2."""
+    import math
+    import numpy as np
+    import workloads
+    rows = []
+    for m, h, steps in [(1, 2.5e-4, 100), (1, 5e-4, 50), (1, 1e-3, 30), (1, 1.5e-3, 24),
+                        (2, 5e-4, 50), (4, 5e-4, 50), (8, 5e-4, 50)]:
+        p = workloads.cold_lattice(mode=m, dt=h, n_steps=steps)
+        wp = math.sqrt(p.N / p.L ** 3)
+        S = math.exp(-0.5 * (2 * math.pi * m * p.a / p.L) ** 2)
+        w_ref = (2.0 / h) * math.asin(wp * h * S / 2.0)
+        idx = _mode_index(p.n_max, m)
+        series = []
+        with sce.Context.from_particles(p, precision="fp32") as c:
+            for _ in range(steps):
+                c.sce_step(h, 1)
+                series.append(c.sce_deposit()[idx].real)
+        t = h * np.arange(1, steps + 1)
+        w = _fit_omega(np.array(series), t, w_ref)
+        rows.append({"m": m, "h": h, "steps": steps, "wp_h_S_over_2": wp * h * S / 2,
+                     "omega": w, "omega_theory": w_ref, "rel_err": w / w_ref - 1,
+                     "omega_continuum": wp * S})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    # unstable: h = 2.5e-3, w_p h S / 2 = 1.28; small amplitude keeps the mode linear
+    h, m = 2.5e-3, 1
+    p = workloads.cold_lattice(mode=m, dt=h, amplitude=1e-4, n_steps=5)
+    wp = math.sqrt(p.N / p.L ** 3)
+    S = math.exp(-0.5 * (2 * math.pi * m * p.a / p.L) ** 2)
+    b = (wp * h * S) ** 2 - 2.0
+    lam = (b + math.sqrt(b * b - 4.0)) / 2.0
+    idx = _mode_index(p.n_max, m)
+    amps = []
+    with sce.Context.from_particles(p, precision="fp64") as c:
+        amps.append(c.sce_deposit()[idx].real)
+        for _ in range(4):
+            c.sce_step(h, 1)
+            amps.append(c.sce_deposit()[idx].real)
+    ratios = [amps[i + 1] / amps[i] for i in range(1, len(amps) - 1)]
+    return {"study": "dispersion",
+            "workload": "cold lattice 128x128x64 (N = 1,048,576), n_max = 32, Gaussian a = 0.01, "
+                        "perturbation A cos(2 pi m x / L), A = 0.01 (1e-4 for the unstable case)",
+            "precision": "fp32 (unstable case fp64)", "stable": rows,
+            "unstable": {"h": h, "wp_h_S_over_2": wp * h * S / 2, "lambda_theory": -lam,
+                         "step_ratios": ratios}}
+
+
+def study_h2(sce):
+    """Two-body problem at fixed T = 1 with h = 4e-3 .. 2.5e-4 (FP64): the largest
+    energy deviation scales as h^2 (Section 6) and the largest single-step
+    change as h^3."""
+    import numpy as np
+    import workloads
+    out = []
+    for h in [4e-3, 2e-3, 1e-3, 5e-4, 2.5e-4]:
+        p = workloads.two_body(dt=h)
+        steps = int(round(1.0 / h))
+        with sce.Context.from_particles(p, precision="fp64") as c:
+            E0 = c.sce_diagnostics()[0].total
+            dev, step_max, prev = 0.0, 0.0, E0
+            for i in range(steps):
+                c.sce_step(h, 1)
+                E = c.sce_diagnostics()[0].total
+                step_max = max(step_max, abs(E - prev))
+                dev = max(dev, abs(E - E0))
+                prev = E
+        out.append({"h": h, "steps": steps, "max_dE": dev, "max_step_dE": step_max, "E0": E0})
+    hs = np.log([r["h"] for r in out])
+    slope = float(np.polyfit(hs, np.log([r["max_dE"] for r in out]), 1)[0])
+    slope1 = float(np.polyfit(hs, np.log([r["max_step_dE"] for r in out]), 1)[0])
+    return {"study": "h2", "workload": "two-body, L = 1, n_max = 8, Gaussian a = 0.05, T = 1, KDK, fp64",
+            "rows": out, "slope_max_dE": slope, "slope_max_step_dE": slope1}
+
+
+def study_longrun(sce, steps, every=1000):
+    """Two-species neutral plasma, N = 262,144, n_max = 16, h = 1e-3: relative
+    energy drift per 1,000 steps (least-squares slope over the second half of the
+    run, relative to |E0| and to the mean kinetic energy there) and the largest
+    momentum error, for each precision."""
+    import numpy as np
+    import workloads
+    p = workloads.two_species()
+    res = {}
+    for prec in ["split_f16", "fp32", "fp64"]:
+        with sce.Context.from_particles(p, precision=prec, scheme="kdk") as c:
+            d = c.sce_diagnostics()[0]
+            P0 = np.array(d.momentum)
+            ts, Es, Ks, perr = [0], [d.total], [d.kinetic], [0.0]
+            t0 = time.perf_counter()
+            for i in range(steps // every):
+                c.sce_step(p.dt, every)
+                d = c.sce_diagnostics()[0]
+                ts.append((i + 1) * every)
+                Es.append(d.total)
+                Ks.append(d.kinetic)
+                perr.append(float(np.max(np.abs(np.array(d.momentum) - P0)) / d.momentum_abs_sum))
+                print(f"{prec} step {ts[-1]} E={d.total:.10e} K={d.kinetic:.6e} perr={perr[-1]:.2e}",
+                      file=sys.stderr, flush=True)
+            wall = time.perf_counter() - t0
+        ts, Es, Ks = np.array(ts), np.array(Es), np.array(Ks)
+        half = ts >= ts[-1] / 2
+        slope = float(np.polyfit(ts[half], Es[half], 1)[0]) * 1000.0
+        res[prec] = {"steps": int(ts[-1]), "ms_per_step": 1e3 * wall / max(ts[-1], 1),
+                     "E0": float(Es[0]), "K0": float(Ks[0]), "K_mean_second_half": float(np.mean(Ks[half])),
+                     "drift_per_1000_rel_E0": slope / abs(Es[0]),
+                     "drift_per_1000_rel_Kbar": slope / float(np.mean(Ks[half])),
+                     "max_dE_rel_E0": float(np.max(np.abs(Es - Es[0])) / abs(Es[0])),
+                     "momentum_err_max": float(np.max(perr))}
+    return {"study": "longrun",
+            "workload": "two-species neutral plasma N = 262,144 (m_ion = 100), n_max = 16, Gaussian a = 0.02, "
+                        "sigma_v = 0.02, h = 1e-3, KDK", "results": res}
+
+
 def cpu_baseline(p, sample):
     import numpy as np
     import oracle
@@ -248,6 +394,15 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.study:
+        if a.study == "longrun":
+            r = study_longrun(sce, a.long_steps)
+        elif a.study == "dispersion":
+            r = study_dispersion(sce)
+        else:
+            r = study_h2(sce)
+        print(json.dumps(r), flush=True)
+        return
     if a.copy_calibration:
         n = a.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

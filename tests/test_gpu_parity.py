@@ -265,6 +265,28 @@ def test_cold_plasma_frequency_at_full_size():
     assert abs(best[1] / w_ref - 1) < 2e-3
 
 
+def test_unstable_time_step_grows_at_the_discrete_rate():
+    """Past the stability limit w_p h S / 2 > 1 (h = 2.5e-3 on the same lattice,
+    w_p h S / 2 = 1.28) the k1 amplitude is multiplied each step by the root
+    lambda of lambda + 1/lambda = 2 - (w_p h S)^2 (Section 5), -4.295 here."""
+    sce = _gpu()
+    p = workloads.cold_lattice(dt=2.5e-3, amplitude=1e-4)
+    wp = math.sqrt(p.N / p.L ** 3)
+    S1 = math.exp(-0.5 * (2 * math.pi * p.a / p.L) ** 2)
+    b = (wp * p.dt * S1) ** 2 - 2.0
+    lam = -(b + math.sqrt(b * b - 4.0)) / 2.0
+    k1 = _k1_index(p.n_max)
+    amps = []
+    with sce.Context.from_particles(p, precision="fp64") as c:
+        amps.append(c.sce_deposit()[k1].real)
+        for _ in range(4):
+            c.sce_step(p.dt, 1)
+            amps.append(c.sce_deposit()[k1].real)
+    ratios = [amps[i + 1] / amps[i] for i in range(len(amps) - 1)]
+    print("ratios", ratios, "lambda", lam)
+    assert all(abs(r / lam - 1) < 5e-3 for r in ratios[2:])
+
+
 def _k1_index(n):
     """Canonical index of mode (1, 0, 0): after the n_x = 0 block (n + n(2n+1)
     modes) and the n_y = -n..-1 rows of n_x = 1, at n_z = 0."""

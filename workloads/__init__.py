@@ -126,11 +126,11 @@ def random_plasma(N: int = 65536, n_max: int = 16, a: float = 0.02, sigma_v: flo
 
 def cold_lattice(nx: int = 128, ny: int = 128, nz: int = 64, n_max: int = 32, a: float = 0.01,
                  amplitude: float = 0.01, jitter: float = 1e-3, dt: float = 5e-4,
-                 n_steps: int = 50, L: float = 1.0, salt: int = 0) -> Particles:
+                 n_steps: int = 50, L: float = 1.0, salt: int = 0, mode: int = 1) -> Particles:
     """Cold electron plasma (q = -1, m = 1, v = 0) on an nx*ny*nz lattice of
     cell-centred sites, each coordinate jittered uniformly in [-jitter, jitter]*L,
-    then displaced along x by xi(x0) = -(A/k1) sin(k1 x0), k1 = 2 pi / L, which
-    realises the density n0 (1 + A cos(k1 x)) to first order in A."""
+    then displaced along x by xi(x0) = -(A/k1) sin(k1 x0), k1 = 2 pi mode / L,
+    which realises the density n0 (1 + A cos(k1 x)) to first order in A."""
     g = _rng("cold_lattice", salt)
     i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
     x0 = (i.ravel() + 0.5) / nx * L
@@ -141,7 +141,7 @@ def cold_lattice(nx: int = 128, ny: int = 128, nz: int = 64, n_max: int = 32, a:
     x0 = x0 + jit[0]
     y0 = y0 + jit[1]
     z0 = z0 + jit[2]
-    k1 = 2.0 * math.pi / L
+    k1 = 2.0 * math.pi * mode / L
     x = x0 - (amplitude / k1) * np.sin(k1 * x0)
     wrap = lambda u: u - L * np.floor(u / L)
     zeros = np.zeros(N)
