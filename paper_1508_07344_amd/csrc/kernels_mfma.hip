@@ -132,54 +132,80 @@ k_deposit_prep(const double *__restrict__ pos, const double *__restrict__ q, int
     o[6 * (nb + 1)] = (float)(q[j] * qfac);
 }
 
-// Table row of particle p in the LDS a/b tables: groups of 8 particles are
-// separated by 4 float2 of padding so that the four lane groups (particles
-// 8g..8g+7) read from distinct banks.
-__device__ inline int tab_row(int p, int n1) { return p * n1 + (p >> 3) * 4; }
+// Rows of particle p in the LDS a (n+1 entries) and b (2n+1 entries) tables:
+// groups of 8 particles are separated by 4 float2 of padding so that the four
+// lane groups (particles 8g..8g+7) read from distinct banks.
+__device__ inline int tab_row(int p, int w) { return p * w + (p >> 3) * 4; }
+
+// Running sums change sign every 2^kDepFlipLog chunks.
+constexpr int kDepFlipLog = 3;
+// FP32 sums of the n_z = 0 row are added into FP64 every 2^kDepDcLog chunks.
+constexpr int kDepDcLog = 4;
+
+// CS rows of the matrix-core operand: cos(n_z theta) for n_z = 1..n (rows
+// 0..n-1), sin(n_z theta) for n_z = 1..n (rows n..2n-1), zero padding to 16s.
+// The n_z = 0 row (all ones) is summed on the VALU instead.
+__host__ __device__ inline int mfma_cs_tiles(int n) { return (2 * n + 15) / 16; }
+
+__host__ __device__ inline size_t dep_buf_bytes(int n, int MT)
+{
+    return (size_t)MT * 16 * kDepChunk * 2 * sizeof(_Float16) +
+           (size_t)(kDepChunk * (n + 1) + 16 + kDepChunk * (2 * n + 1) + 16) * sizeof(float2);
+}
 
 // Block = 8 waves = 256 rows (two 16-row N tiles per wave), all CS rows
-// (MT tiles of 16); blockIdx.y = particle split.  Per chunk of 32 particles
-// the block builds LDS tables from the particle records (each thread's record
-// fields prefetched one chunk ahead): a = q cis(-nx tx), b = cis(-k ty) (FP32)
-// and the CS operand as FP16 hi/lo; each lane then forms its own H fragment.
+// (MT tiles of 16); blockIdx.y = particle split, visited in the pseudo-random
+// order of the particle records.  Per chunk of 32 particles the block builds
+// LDS tables from the records: a = q cis(-k tx) for k = 0..n, b = cis(-k ty)
+// for k = -n..n (FP32), and the CS operand as FP16 hi/lo.  Tables are double
+// buffered: while every wave multiplies chunk c out of one buffer, the next
+// chunk's tables go into the other, so one barrier per chunk suffices.  Each
+// lane forms its own H = a b fragment (8 particles x 1 row), splits it into
+// hi/lo and adds its n_z = 0 contribution on the VALU.
 template <int MT>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512, 2)
 k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
-               int64_t per_split, double unscale, double *__restrict__ part)
+               int64_t per_split, double unscale_mf, double unscale_dc, double *__restrict__ part)
 {
     typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
     typedef float float2_t __attribute__((ext_vector_type(2)));
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n1 = n + 1;
-    const int CSR = MT * 16;  // CS rows incl. padding
-    const int trows = kDepChunk * n1 + 16;
-    _Float16 *cs_hi = reinterpret_cast<_Float16 *>(smem);            // [CSR][32]
-    _Float16 *cs_lo = cs_hi + CSR * kDepChunk;                        // [CSR][32]
-    float2 *ta = reinterpret_cast<float2 *>(cs_lo + CSR * kDepChunk);  // tab_row(p) + k
-    float2 *tb = ta + trows;
+    const int n1 = n + 1, M = 2 * n + 1;
+    constexpr int CSR = MT * 16;
+    const size_t bufb = dep_buf_bytes(n, MT);
+    auto cs_hi = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb); };
+    auto cs_lo = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb) + CSR * kDepChunk; };
+    auto tab_a = [&](int b) {
+        return reinterpret_cast<float2 *>(smem + b * bufb + (size_t)CSR * kDepChunk * 2 * sizeof(_Float16));
+    };
+    auto tab_b = [&](int b) { return tab_a(b) + kDepChunk * n1 + 16; };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4;   // lane group: particles 8g..8g+7 of a chunk
     const int ln = lane & 15;  // row within an N tile
     const int64_t j0 = (int64_t)blockIdx.y * per_split;
     const int64_t j1 = j0 + per_split < N ? j0 + per_split : N;
+    const int64_t nchunks = (j1 - j0 + kDepChunk - 1) / kDepChunk;
     const int nb = (n1 + 7) / 8;
     const int rf = dep_rec_floats(n);
 
-    for (int idx = tid; idx < (CSR - (2 * n + 1)) * kDepChunk; idx += 512) {
-        cs_hi[(2 * n + 1) * kDepChunk + idx] = (_Float16)0.0f;
-        cs_lo[(2 * n + 1) * kDepChunk + idx] = (_Float16)0.0f;
-    }
+    for (int idx = tid; idx < (CSR - 2 * n) * kDepChunk; idx += 512)
+        for (int b = 0; b < 2; ++b) {
+            cs_hi(b)[2 * n * kDepChunk + idx] = (_Float16)0.0f;
+            cs_lo(b)[2 * n * kDepChunk + idx] = (_Float16)0.0f;
+        }
 
-    int rnx[2], rny[2];
+    int rnx[2], rnyo[2];
     bool rok[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
         const int r = blockIdx.x * kDepRowsPerBlock + wave * 32 + nt * 16 + ln;
         rok[nt] = r < R;
-        row_nxny(r < R ? r : R - 1, n, rnx[nt], rny[nt]);
+        int ny;
+        row_nxny(r < R ? r : R - 1, n, rnx[nt], ny);
+        rnyo[nt] = ny + n;  // column of k = ny in the b table
     }
 
     f32x4 acc[MT][2][2];
@@ -187,105 +213,100 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) acc[mt][nt][0] = acc[mt][nt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+    double dcd[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
 
-    // table tasks (axis d, block blk, particle p), particle fastest
+    // table tasks (axis d, block of 8 powers blk, particle p), particle fastest;
+    // thread tid owns tasks tid, tid + 512, ...; its first task's record
+    // fields are fetched one chunk ahead, further tasks (n_max >= 40) load theirs
     const int ntask = 3 * nb * kDepChunk;
-    const int t_p = tid & (kDepChunk - 1);
-    const int t_db = tid / kDepChunk;
-    const int t_d = t_db / nb, t_blk = t_db - t_d * nb;
-    float pa_c = 1.f, pa_s = 0.f, ps_c = 1.f, ps_s = 0.f, pq = 0.f;
-    auto fetch = [&](int64_t cbase) {
-        pa_c = 1.f;
-        pa_s = 0.f;
-        ps_c = 1.f;
-        ps_s = 0.f;
-        pq = 0.f;
-        if (tid < ntask && cbase + t_p < j1) {
-            const float *r0 = rec + (cbase + t_p) * rf;
-            pa_c = r0[2 * (t_d * nb + t_blk)];
-            pa_s = r0[2 * (t_d * nb + t_blk) + 1];
-            ps_c = r0[2 * (3 * nb + t_d)];
-            ps_s = r0[2 * (3 * nb + t_d) + 1];
-            pq = r0[6 * (nb + 1)];
+    float pa_c, pa_s, ps_c, ps_s, pq;
+    auto load_task = [&](int task, int64_t c, float &fc, float &fs, float &sc, float &ss, float &fq) {
+        fc = 1.f;
+        fs = 0.f;
+        sc = 1.f;
+        ss = 0.f;
+        fq = 0.f;
+        const int p = task & (kDepChunk - 1);
+        const int db = task / kDepChunk;
+        const int d = db / nb, blk = db - d * nb;
+        const int64_t j = j0 + c * kDepChunk + p;
+        if (task < ntask && c < nchunks && j < j1) {
+            const float *r0 = rec + j * rf;
+            fc = r0[2 * (d * nb + blk)];
+            fs = r0[2 * (d * nb + blk) + 1];
+            sc = r0[2 * (3 * nb + d)];
+            ss = r0[2 * (3 * nb + d) + 1];
+            fq = r0[6 * (nb + 1)];
         }
     };
-    fetch(j0);
-
-    int64_t chunk = 0;
-    for (int64_t base = j0; base < j1; base += kDepChunk, ++chunk) {
-        const bool neg = ((chunk >> 2) & 1) != 0;
-        const float csg = neg ? -kDepOpScale : kDepOpScale;
-        __syncthreads();  // previous chunk's tables are no longer read
-        for (int task = tid; task < ntask; task += 512) {
-            int p, d, blk;
-            float fc, fs, sc, ss, fq;
-            if (task == tid) {
-                p = t_p;
-                d = t_d;
-                blk = t_blk;
-                fc = pa_c;
-                fs = pa_s;
-                sc = ps_c;
-                ss = ps_s;
-                fq = pq;
-            } else {
-                p = task & (kDepChunk - 1);
-                const int db = task / kDepChunk;
-                d = db / nb;
-                blk = db - d * nb;
-                fc = 1.f;
-                fs = 0.f;
-                sc = 1.f;
-                ss = 0.f;
-                fq = 0.f;
-                if (base + p < j1) {
-                    const float *r0 = rec + (base + p) * rf;
-                    fc = r0[2 * (d * nb + blk)];
-                    fs = r0[2 * (d * nb + blk) + 1];
-                    sc = r0[2 * (3 * nb + d)];
-                    ss = r0[2 * (3 * nb + d) + 1];
-                    fq = r0[6 * (nb + 1)];
-                }
+    auto fetch = [&](int64_t c) { load_task(tid, c, pa_c, pa_s, ps_c, ps_s, pq); };
+    // tables of chunk c into buffer c & 1
+    auto build_task = [&](int task, int64_t c, float fc, float fs, float sc, float ss, float fq) {
+        const int b = (int)(c & 1);
+        const int p = task & (kDepChunk - 1);
+        const int db = task / kDepChunk;
+        const int d = db / nb, blk = db - d * nb;
+        const int k0 = 8 * blk;
+        const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
+        if (d == 0) {
+            float2 *dst = tab_a(b) + tab_row(p, n1) + k0;
+            for (int kk = 0; kk < kend; ++kk) {
+                dst[kk] = make_float2(fq * fc, -fq * fs);
+                const float t = fc * sc - fs * ss;
+                fs = fc * ss + fs * sc;
+                fc = t;
             }
-            const int k0 = 8 * blk;
-            const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
-            if (d == 0) {
-                float2 *dst = ta + tab_row(p, n1) + k0;
-                for (int kk = 0; kk < kend; ++kk) {
-                    dst[kk] = make_float2(fq * fc, -fq * fs);
-                    const float t = fc * sc - fs * ss;
-                    fs = fc * ss + fs * sc;
-                    fc = t;
-                }
-            } else if (d == 1) {
-                float2 *dst = tb + tab_row(p, n1) + k0;
-                for (int kk = 0; kk < kend; ++kk) {
-                    dst[kk] = make_float2(fc, -fs);
-                    const float t = fc * sc - fs * ss;
-                    fs = fc * ss + fs * sc;
-                    fc = t;
-                }
-            } else {
-                for (int kk = 0; kk < kend; ++kk) {
-                    const int k = k0 + kk;
+        } else if (d == 1) {
+            float2 *dst = tab_b(b) + tab_row(p, M) + n;
+            for (int kk = 0; kk < kend; ++kk) {
+                const int k = k0 + kk;
+                dst[k] = make_float2(fc, -fs);
+                dst[-k] = make_float2(fc, fs);
+                const float t = fc * sc - fs * ss;
+                fs = fc * ss + fs * sc;
+                fc = t;
+            }
+        } else {
+            const float csg = ((c >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
+            _Float16 *hi = cs_hi(b), *lo = cs_lo(b);
+            for (int kk = 0; kk < kend; ++kk) {
+                const int k = k0 + kk;
+                if (k > 0) {
                     _Float16 h, l;
                     split_f16(csg * fc, h, l);
-                    cs_hi[k * kDepChunk + p] = h;
-                    cs_lo[k * kDepChunk + p] = l;
-                    if (k > 0) {
-                        split_f16(csg * fs, h, l);
-                        cs_hi[(n + k) * kDepChunk + p] = h;
-                        cs_lo[(n + k) * kDepChunk + p] = l;
-                    }
-                    const float t = fc * sc - fs * ss;
-                    fs = fc * ss + fs * sc;
-                    fc = t;
+                    hi[(k - 1) * kDepChunk + p] = h;
+                    lo[(k - 1) * kDepChunk + p] = l;
+                    split_f16(csg * fs, h, l);
+                    hi[(n + k - 1) * kDepChunk + p] = h;
+                    lo[(n + k - 1) * kDepChunk + p] = l;
                 }
+                const float t = fc * sc - fs * ss;
+                fs = fc * ss + fs * sc;
+                fc = t;
             }
         }
-        fetch(base + kDepChunk);
-        __syncthreads();
-        if (chunk > 0 && (chunk & 3) == 0) {
+    };
+    auto build = [&](int64_t c) {
+        if (tid < ntask) build_task(tid, c, pa_c, pa_s, ps_c, ps_s, pq);
+        for (int task = tid + 512; task < ntask; task += 512) {
+            float fc, fs, sc, ss, fq;
+            load_task(task, c, fc, fs, sc, ss, fq);
+            build_task(task, c, fc, fs, sc, ss, fq);
+        }
+    };
+
+    fetch(0);
+    build(0);
+    fetch(1);
+    __syncthreads();
+    for (int64_t c = 0; c < nchunks; ++c) {
+        const int b = (int)(c & 1);
+        if (c + 1 < nchunks) {
+            build(c + 1);
+            fetch(c + 2);
+        }
+        if (c > 0 && (c & ((1 << kDepFlipLog) - 1)) == 0) {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -294,31 +315,26 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                     acc[mt][nt][1] = -acc[mt][nt][1];
                 }
         }
-        half8 ah[MT], al[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            ah[mt] = *reinterpret_cast<const half8 *>(&cs_hi[(mt * 16 + ln) * kDepChunk + 8 * g]);
-            al[mt] = *reinterpret_cast<const half8 *>(&cs_lo[(mt * 16 + ln) * kDepChunk + 8 * g]);
-        }
+        const float2 *ta = tab_a(b), *tb = tab_b(b);
+        const _Float16 *chi = cs_hi(b), *clo = cs_lo(b);
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) {
             half8 bre_h, bre_l, bim_h, bim_l;
-            const int ay = rny[nt] < 0 ? -rny[nt] : rny[nt];
-            const float sgn = rny[nt] < 0 ? -1.0f : 1.0f;
-            const float zero = rok[nt] ? 1.0f : 0.0f;
+            float sre = 0.f, sim = 0.f;
 #pragma unroll
             for (int i = 0; i < 8; i += 2) {
                 const int p0 = 8 * g + i;
                 const float2 a0 = ta[tab_row(p0, n1) + rnx[nt]];
-                const float2 b0 = tb[tab_row(p0, n1) + ay];
+                const float2 b0 = tb[tab_row(p0, M) + rnyo[nt]];
                 const float2 a1 = ta[tab_row(p0 + 1, n1) + rnx[nt]];
-                const float2 b1 = tb[tab_row(p0 + 1, n1) + ay];
-                const float b0y = sgn * b0.y, b1y = sgn * b1.y;
+                const float2 b1 = tb[tab_row(p0 + 1, M) + rnyo[nt]];
                 float2_t hr, hm;
-                hr[0] = zero * (a0.x * b0.x - a0.y * b0y);
-                hm[0] = zero * (a0.x * b0y + a0.y * b0.x);
-                hr[1] = zero * (a1.x * b1.x - a1.y * b1y);
-                hm[1] = zero * (a1.x * b1y + a1.y * b1.x);
+                hr[0] = a0.x * b0.x - a0.y * b0.y;
+                hm[0] = a0.x * b0.y + a0.y * b0.x;
+                hr[1] = a1.x * b1.x - a1.y * b1.y;
+                hm[1] = a1.x * b1.y + a1.y * b1.x;
+                sre += hr[0] + hr[1];
+                sim += hm[0] + hm[1];
                 const half2_t rh = __builtin_convertvector(hr, half2_t);
                 const half2_t mh = __builtin_convertvector(hm, half2_t);
                 const half2_t rl = __builtin_convertvector(hr - __builtin_convertvector(rh, float2_t), half2_t);
@@ -332,57 +348,71 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                 bim_l[i] = ml[0];
                 bim_l[i + 1] = ml[1];
             }
+            dc[nt][0] += sre;
+            dc[nt][1] += sim;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                acc[mt][nt][0] = mfma_split(ah[mt], al[mt], bre_h, bre_l, acc[mt][nt][0]);
-                acc[mt][nt][1] = mfma_split(ah[mt], al[mt], bim_h, bim_l, acc[mt][nt][1]);
+                const half8 ah = *reinterpret_cast<const half8 *>(&chi[(mt * 16 + ln) * kDepChunk + 8 * g]);
+                const half8 al = *reinterpret_cast<const half8 *>(&clo[(mt * 16 + ln) * kDepChunk + 8 * g]);
+                acc[mt][nt][0] = mfma_split(ah, al, bre_h, bre_l, acc[mt][nt][0]);
+                acc[mt][nt][1] = mfma_split(ah, al, bim_h, bim_l, acc[mt][nt][1]);
             }
         }
+        if ((c & ((1 << kDepDcLog) - 1)) == ((1 << kDepDcLog) - 1)) {
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) {
+                dcd[nt][0] += (double)dc[nt][0];
+                dcd[nt][1] += (double)dc[nt][1];
+                dc[nt][0] = dc[nt][1] = 0.f;
+            }
+        }
+        __syncthreads();
     }
 
-    // after chunk c the running sums carry the sign (-1)^((c >> 2) & 1)
-    const int64_t last = (j1 - j0 + kDepChunk - 1) / kDepChunk - 1;
-    const double fsign = ((last >> 2) & 1) ? -1.0 : 1.0;
-    const double outscale = unscale * fsign;
+    // after chunk c the running sums carry the sign (-1)^((c >> kDepFlipLog) & 1)
+    const int64_t last = nchunks - 1;
+    const double fsign = last >= 0 && ((last >> kDepFlipLog) & 1) ? -1.0 : 1.0;
+    const double outscale = unscale_mf * fsign;
     double *pb = part + (int64_t)blockIdx.y * (int64_t)n1 * 4 * Rpad;
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
+        // n_z = 0: the four lane groups' sums, added in a fixed order
+        double dre = dcd[nt][0] + (double)dc[nt][0], dim = dcd[nt][1] + (double)dc[nt][1];
+        dre += __shfl_xor(dre, 16, 64);
+        dim += __shfl_xor(dim, 16, 64);
+        dre += __shfl_xor(dre, 32, 64);
+        dim += __shfl_xor(dim, 32, 64);
         const int r = blockIdx.x * kDepRowsPerBlock + wave * 32 + nt * 16 + ln;
         if (!rok[nt]) continue;
+        if (g == 0) {
+            pb[0 * Rpad + r] = unscale_dc * dre;
+            pb[1 * (int64_t)Rpad + r] = unscale_dc * dim;
+            pb[2 * (int64_t)Rpad + r] = 0.0;
+            pb[3 * (int64_t)Rpad + r] = 0.0;
+        }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int m = mt * 16 + 4 * g + i;
                 int nz, slot;
-                if (m <= n) {
-                    nz = m;
+                if (m < n) {
+                    nz = m + 1;
                     slot = 0;
-                } else if (m <= 2 * n) {
-                    nz = m - n;
+                } else if (m < 2 * n) {
+                    nz = m - n + 1;
                     slot = 2;
                 } else {
                     continue;
                 }
                 pb[((int64_t)nz * 4 + slot) * Rpad + r] = outscale * (double)acc[mt][nt][0][i];
                 pb[((int64_t)nz * 4 + slot + 1) * Rpad + r] = outscale * (double)acc[mt][nt][1][i];
-                if (m == 0) {
-                    pb[((int64_t)0 * 4 + 2) * Rpad + r] = 0.0;
-                    pb[((int64_t)0 * 4 + 3) * Rpad + r] = 0.0;
-                }
             }
         }
     }
 }
 
-int mfma_cs_tiles(int n) { return (2 * n + 1 + 15) / 16; }
-
-size_t deposit_mfma_lds(int n)
-{
-    const int n1 = n + 1;
-    return (size_t)mfma_cs_tiles(n) * 16 * kDepChunk * 2 * sizeof(_Float16) +
-           (size_t)2 * (kDepChunk * n1 + 16) * sizeof(float2);
-}
+size_t deposit_mfma_lds(int n) { return 2 * dep_buf_bytes(n, mfma_cs_tiles(n)); }
 
 MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
 {
@@ -405,11 +435,12 @@ MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
 
 template <int MT>
 static void launch_dep_mt(hipStream_t s, const float *rec, int64_t N, const Geom &g,
-                          const MfmaDepositPlan &pl, double unscale, double *part)
+                          const MfmaDepositPlan &pl, double unscale_mf, double unscale_dc,
+                          double *part)
 {
     hipLaunchKernelGGL(k_deposit_mfma<MT>, dim3(pl.row_blocks, pl.splits), dim3(512),
-                       deposit_mfma_lds(g.n), s, rec, N, g.n, g.R, g.Rpad, pl.per_split, unscale,
-                       part);
+                       deposit_mfma_lds(g.n), s, rec, N, g.n, g.R, g.Rpad, pl.per_split,
+                       unscale_mf, unscale_dc, part);
 }
 
 size_t deposit_mfma_rec_bytes(int64_t N, int n) { return (size_t)N * dep_rec_floats(n) * sizeof(float); }
@@ -420,17 +451,18 @@ hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q
 {
     hipLaunchKernelGGL(k_deposit_prep, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, pos, q,
                        N, g.n, 1.0 / L, (int)pl.perm, (double)kDepOpScale / qscale, rec);
-    const double unscale = qscale / ((double)kDepOpScale * (double)kDepOpScale);
+    // H carries q / qscale scaled by 7/8, the CS operand another 7/8
+    const double unscale_dc = qscale / (double)kDepOpScale;
+    const double unscale_mf = unscale_dc / (double)kDepOpScale;
     switch (mfma_cs_tiles(g.n)) {
-    case 1: launch_dep_mt<1>(s, rec, N, g, pl, unscale, part); break;
-    case 2: launch_dep_mt<2>(s, rec, N, g, pl, unscale, part); break;
-    case 3: launch_dep_mt<3>(s, rec, N, g, pl, unscale, part); break;
-    case 4: launch_dep_mt<4>(s, rec, N, g, pl, unscale, part); break;
-    case 5: launch_dep_mt<5>(s, rec, N, g, pl, unscale, part); break;
-    case 6: launch_dep_mt<6>(s, rec, N, g, pl, unscale, part); break;
-    case 7: launch_dep_mt<7>(s, rec, N, g, pl, unscale, part); break;
-    case 8: launch_dep_mt<8>(s, rec, N, g, pl, unscale, part); break;
-    default: launch_dep_mt<9>(s, rec, N, g, pl, unscale, part); break;
+    case 1: launch_dep_mt<1>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
+    case 2: launch_dep_mt<2>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
+    case 3: launch_dep_mt<3>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
+    case 4: launch_dep_mt<4>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
+    case 5: launch_dep_mt<5>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
+    case 6: launch_dep_mt<6>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
+    case 7: launch_dep_mt<7>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
+    default: launch_dep_mt<8>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
     }
     return hipGetLastError();
 }
@@ -516,11 +548,25 @@ hipError_t launch_force_pack(hipStream_t s, const float *ftab, const Geom &g, fl
 
 // ------------------------------------------------------------------ force
 // Block = 4 waves x 64 particles (NT = 4 N tiles of 16 particles per wave).
-// The W fragments of TM row quads at a time are staged in LDS for the whole
-// block; every wave keeps its particles' CS fragments in registers.  The lane
-// group g = l/16 handles row 4t + g of each quad t, so the four groups sum
-// disjoint rows of the same particles and are combined at the end.
-constexpr int kForceTM = 8;
+// The W fragments of kForceTM row quads at a time are copied into LDS for the
+// whole block with direct global-to-LDS loads, double buffered: the next
+// quads' fragments stream in while the current ones are multiplied, one
+// barrier per kForceTM quads.  Every wave keeps its particles' CS fragments
+// in registers.  The lane group g = l/16 handles row 4t + g of each quad t, so
+// the four groups sum disjoint rows of the same particles and are combined at
+// the end.  Per-quad sums are FP32 and are added into FP64 once per kForceTM quads.
+constexpr int kForceTM = 4;
+
+// Copy pieces [0, npieces) of 64 half8 (1 KB) from src to LDS dst, piece p by
+// wave p % 4: lane l moves the 16 bytes at src[64 p + l] to dst[64 p + l].
+__device__ inline void stage_w(const half8 *__restrict__ src, half8 *dst, int npieces, int wave,
+                               int lane)
+{
+    for (int p = wave; p < npieces; p += 4)
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(src + 64 * p + lane),
+            (__attribute__((address_space(3))) void *)(dst + 64 * p), 16, 0, 0);
+}
 
 template <int KS>
 __global__ void __launch_bounds__(256)
@@ -531,17 +577,23 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
              double *__restrict__ phi)
 {
     constexpr int NT = 4;
+    constexpr int PIECES = kForceTM * KS * 2;  // 1 KB pieces per stage
     extern __shared__ __align__(16) unsigned char smem[];
-    half8 *wl = reinterpret_cast<half8 *>(smem);  // [TM][KS][2][64]
+    half8 *wl0 = reinterpret_cast<half8 *>(smem);  // [2][TM][KS][2][64]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4;
     const int ln = lane & 15;
     const int nzk = 16 * KS;
+    const int M = 2 * n + 1;
+    const half8 *wsrc = reinterpret_cast<const half8 *>(wf);
+    const int nstage = (quads + kForceTM - 1) / kForceTM;
 
-    // per N tile: particle, turns, CS fragments, phase state
+    // first stage in flight while the particle fragments are formed
+    stage_w(wsrc, wl0, (quads < kForceTM ? quads : kForceTM) * KS * 2, wave, lane);
+
     half8 bh[NT][KS], bl[NT][KS];
     double tx[NT], ty[NT];
     float gc[NT], gs[NT], e4c[NT], e4s[NT];
@@ -580,7 +632,8 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
         e4s[nt] = (float)b;
         fx[nt] = fy[nt] = fz[nt] = fp[nt] = 0.0;
     }
-    // lane group g starts at row g
+    // lane group g starts at row g; rows advance by 4 with (nx, ny) tracked
+    // incrementally (a line n_x >= 0 ends at n_y = n, the next starts at -n)
     int r = g;
     int nx, ny;
     row_nxny(r < R ? r : R - 1, n, nx, ny);
@@ -592,15 +645,21 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
         gs[nt] = (float)b;
     }
 
-    for (int t0 = 0; t0 < quads; t0 += kForceTM) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int st = 0; st < nstage; ++st) {
+        const int t0 = st * kForceTM;
         const int tcnt = quads - t0 < kForceTM ? quads - t0 : kForceTM;
-        __syncthreads();
-        {
-            const half8 *src = reinterpret_cast<const half8 *>(wf) + (int64_t)t0 * KS * 2 * 64;
-            const int total = tcnt * KS * 2 * 64;
-            for (int i = tid; i < total; i += 256) wl[i] = src[i];
+        const half8 *wl = wl0 + (st & 1) * PIECES * 64;
+        if (st + 1 < nstage) {
+            const int t1 = t0 + kForceTM;
+            const int c1 = quads - t1 < kForceTM ? quads - t1 : kForceTM;
+            stage_w(wsrc + (int64_t)t1 * KS * 2 * 64, wl0 + ((st + 1) & 1) * PIECES * 64, c1 * KS * 2,
+                    wave, lane);
         }
-        __syncthreads();
+        float sx[NT], sy[NT], sz[NT], sp[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) sx[nt] = sy[nt] = sz[nt] = sp[nt] = 0.f;
         for (int tt = 0; tt < tcnt; ++tt) {
             half8 ah[KS], al[KS];
 #pragma unroll
@@ -615,27 +674,26 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
                 p0i = psi0[2 * r + 1];
                 wscale = rowscale[r];
             }
-            const double dnx = (double)nx, dny = (double)ny;
+            const float fnx = (float)nx, fny = (float)ny;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int s = 0; s < KS; ++s) acc = mfma_split(ah[s], al[s], bh[nt][s], bl[nt][s], acc);
-                const float u0r = acc[0] * wscale + p0r, u0i = acc[1] * wscale + p0i;
+                const float u0r = fmaf(acc[0], wscale, p0r), u0i = fmaf(acc[1], wscale, p0i);
                 const float u1r = acc[2] * wscale, u1i = acc[3] * wscale;
-                const double im0 = (double)(gc[nt] * u0i + gs[nt] * u0r);
-                const double re0 = (double)(gc[nt] * u0r - gs[nt] * u0i);
-                const double im1 = (double)(gc[nt] * u1i + gs[nt] * u1r);
-                fx[nt] = fma(dnx, im0, fx[nt]);
-                fy[nt] = fma(dny, im0, fy[nt]);
-                fz[nt] += im1;
-                fp[nt] += re0;
+                const float im0 = gc[nt] * u0i + gs[nt] * u0r;
+                const float re0 = gc[nt] * u0r - gs[nt] * u0i;
+                const float im1 = gc[nt] * u1i + gs[nt] * u1r;
+                sx[nt] = fmaf(fnx, im0, sx[nt]);
+                sy[nt] = fmaf(fny, im0, sy[nt]);
+                sz[nt] += im1;
+                sp[nt] += re0;
             }
             // next row of this lane group: r + 4
             r += 4;
-            int nnx, nny;
-            row_nxny(r < R ? r : R - 1, n, nnx, nny);
-            if (nnx == nx) {
+            ny += 4;
+            if (ny <= n) {
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
                     const float c = gc[nt] * e4c[nt] - gs[nt] * e4s[nt];
@@ -643,17 +701,29 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
                     gc[nt] = c;
                 }
             } else {
+                while (ny > n) {
+                    ny -= M;
+                    ++nx;
+                }
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
                     double a, b;
-                    cis_turns(frac_lin(nnx, tx[nt], nny, ty[nt]), a, b);
+                    cis_turns(frac_lin(nx, tx[nt], ny, ty[nt]), a, b);
                     gc[nt] = (float)a;
                     gs[nt] = (float)b;
                 }
             }
-            nx = nnx;
-            ny = nny;
         }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            fx[nt] += (double)sx[nt];
+            fy[nt] += (double)sy[nt];
+            fz[nt] += (double)sz[nt];
+            fp[nt] += (double)sp[nt];
+        }
+        // the next stage's copies have landed, and every wave is done with this one
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
     }
     // combine the four lane groups (same particles, disjoint rows)
 #pragma unroll
@@ -692,7 +762,7 @@ hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, 
     const int quads = (g.R + 3) / 4;
     const int ks = (g.n + 15) / 16;
     const int64_t blocks = (N + 255) / 256;
-    const size_t lds = (size_t)kForceTM * ks * 2 * 64 * sizeof(half8);
+    const size_t lds = (size_t)2 * kForceTM * ks * 2 * 64 * sizeof(half8);
     switch (ks) {
     case 1:
         hipLaunchKernelGGL(k_force_mfma<1>, dim3((unsigned)blocks), dim3(256), lds, s, pos, q, m,

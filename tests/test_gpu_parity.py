@@ -54,6 +54,7 @@ def _cases():
         ("plasma16", workloads.random_plasma(N=3001, n_max=16, a=0.02)),
         ("plasma32", workloads.random_plasma(N=4099, n_max=32, a=0.01)),
         ("n40", workloads.random_particles(700, L=1.0, charge="alternating").with_(n_max=40, a=0.01)),
+        ("n64", workloads.random_particles(257, L=1.3, charge="uniform").with_(n_max=64, a=0.01)),
     ]
 
 
