@@ -132,10 +132,17 @@ k_deposit_prep(const double *__restrict__ pos, const double *__restrict__ q, int
     o[6 * (nb + 1)] = (float)(q[j] * qfac);
 }
 
-// Rows of particle p in the LDS a (n+1 entries) and b (2n+1 entries) tables:
-// groups of 8 particles are separated by 4 float2 of padding so that the four
-// lane groups (particles 8g..8g+7) read from distinct banks.
-__device__ inline int tab_row(int p, int w) { return p * w + (p >> 3) * 4; }
+// LDS table layouts of the deposit.  Row of particle p in the a table (n+1
+// entries): groups of 8 particles separated by 4 float2, so the four lane
+// groups (particles 8g..8g+7) start in different banks.  b table (2n+1
+// entries): the group padding makes the groups' rows start 128 bytes apart
+// modulo the 256-byte bank cycle, so that lane groups 0/1 and 2/3, which read
+// 16 consecutive entries each in the same pass, use disjoint banks.  CS rows
+// hold 32 particles plus 8 halves of padding (80-byte stride), so that the 16
+// rows read by a lane group's 16-byte fragment loads fall in distinct banks.
+__host__ __device__ inline int tab_pad_b(int n) { return ((2 * n + 1) & 3) == 1 ? 8 : 24; }
+__device__ inline int tab_row(int p, int w, int pad) { return p * w + (p >> 3) * pad; }
+constexpr int kCSP = kDepChunk + 8;
 
 // Running sums change sign every 2^kDepFlipLog chunks.
 constexpr int kDepFlipLog = 3;
@@ -149,8 +156,9 @@ __host__ __device__ inline int mfma_cs_tiles(int n) { return (2 * n + 15) / 16; 
 
 __host__ __device__ inline size_t dep_buf_bytes(int n, int MT)
 {
-    return (size_t)MT * 16 * kDepChunk * 2 * sizeof(_Float16) +
-           (size_t)(kDepChunk * (n + 1) + 16 + kDepChunk * (2 * n + 1) + 16) * sizeof(float2);
+    return (size_t)MT * 16 * kCSP * 2 * sizeof(_Float16) +
+           (size_t)(kDepChunk * (n + 1) + 16 + kDepChunk * (2 * n + 1) + 4 * tab_pad_b(n)) *
+               sizeof(float2);
 }
 
 // Block = 8 waves = 256 rows (two 16-row N tiles per wave), all CS rows
@@ -174,10 +182,11 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     constexpr int CSR = MT * 16;
     const size_t bufb = dep_buf_bytes(n, MT);
     auto cs_hi = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb); };
-    auto cs_lo = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb) + CSR * kDepChunk; };
+    auto cs_lo = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb) + CSR * kCSP; };
     auto tab_a = [&](int b) {
-        return reinterpret_cast<float2 *>(smem + b * bufb + (size_t)CSR * kDepChunk * 2 * sizeof(_Float16));
+        return reinterpret_cast<float2 *>(smem + b * bufb + (size_t)CSR * kCSP * 2 * sizeof(_Float16));
     };
+    const int padb = tab_pad_b(n);
     auto tab_b = [&](int b) { return tab_a(b) + kDepChunk * n1 + 16; };
 
     const int tid = threadIdx.x;
@@ -191,10 +200,10 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     const int nb = (n1 + 7) / 8;
     const int rf = dep_rec_floats(n);
 
-    for (int idx = tid; idx < (CSR - 2 * n) * kDepChunk; idx += 512)
+    for (int idx = tid; idx < (CSR - 2 * n) * kCSP; idx += 512)
         for (int b = 0; b < 2; ++b) {
-            cs_hi(b)[2 * n * kDepChunk + idx] = (_Float16)0.0f;
-            cs_lo(b)[2 * n * kDepChunk + idx] = (_Float16)0.0f;
+            cs_hi(b)[2 * n * kCSP + idx] = (_Float16)0.0f;
+            cs_lo(b)[2 * n * kCSP + idx] = (_Float16)0.0f;
         }
 
     int rnx[2], rnyo[2];
@@ -250,7 +259,7 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
         const int k0 = 8 * blk;
         const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
         if (d == 0) {
-            float2 *dst = tab_a(b) + tab_row(p, n1) + k0;
+            float2 *dst = tab_a(b) + tab_row(p, n1, 4) + k0;
             for (int kk = 0; kk < kend; ++kk) {
                 dst[kk] = make_float2(fq * fc, -fq * fs);
                 const float t = fc * sc - fs * ss;
@@ -258,7 +267,7 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                 fc = t;
             }
         } else if (d == 1) {
-            float2 *dst = tab_b(b) + tab_row(p, M) + n;
+            float2 *dst = tab_b(b) + tab_row(p, M, padb) + n;
             for (int kk = 0; kk < kend; ++kk) {
                 const int k = k0 + kk;
                 dst[k] = make_float2(fc, -fs);
@@ -275,11 +284,11 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                 if (k > 0) {
                     _Float16 h, l;
                     split_f16(csg * fc, h, l);
-                    hi[(k - 1) * kDepChunk + p] = h;
-                    lo[(k - 1) * kDepChunk + p] = l;
+                    hi[(k - 1) * kCSP + p] = h;
+                    lo[(k - 1) * kCSP + p] = l;
                     split_f16(csg * fs, h, l);
-                    hi[(n + k - 1) * kDepChunk + p] = h;
-                    lo[(n + k - 1) * kDepChunk + p] = l;
+                    hi[(n + k - 1) * kCSP + p] = h;
+                    lo[(n + k - 1) * kCSP + p] = l;
                 }
                 const float t = fc * sc - fs * ss;
                 fs = fc * ss + fs * sc;
@@ -324,10 +333,10 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
 #pragma unroll
             for (int i = 0; i < 8; i += 2) {
                 const int p0 = 8 * g + i;
-                const float2 a0 = ta[tab_row(p0, n1) + rnx[nt]];
-                const float2 b0 = tb[tab_row(p0, M) + rnyo[nt]];
-                const float2 a1 = ta[tab_row(p0 + 1, n1) + rnx[nt]];
-                const float2 b1 = tb[tab_row(p0 + 1, M) + rnyo[nt]];
+                const float2 a0 = ta[tab_row(p0, n1, 4) + rnx[nt]];
+                const float2 b0 = tb[tab_row(p0, M, padb) + rnyo[nt]];
+                const float2 a1 = ta[tab_row(p0 + 1, n1, 4) + rnx[nt]];
+                const float2 b1 = tb[tab_row(p0 + 1, M, padb) + rnyo[nt]];
                 float2_t hr, hm;
                 hr[0] = a0.x * b0.x - a0.y * b0.y;
                 hm[0] = a0.x * b0.y + a0.y * b0.x;
@@ -352,8 +361,8 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
             dc[nt][1] += sim;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                const half8 ah = *reinterpret_cast<const half8 *>(&chi[(mt * 16 + ln) * kDepChunk + 8 * g]);
-                const half8 al = *reinterpret_cast<const half8 *>(&clo[(mt * 16 + ln) * kDepChunk + 8 * g]);
+                const half8 ah = *reinterpret_cast<const half8 *>(&chi[(mt * 16 + ln) * kCSP + 8 * g]);
+                const half8 al = *reinterpret_cast<const half8 *>(&clo[(mt * 16 + ln) * kCSP + 8 * g]);
                 acc[mt][nt][0] = mfma_split(ah, al, bre_h, bre_l, acc[mt][nt][0]);
                 acc[mt][nt][1] = mfma_split(ah, al, bim_h, bim_l, acc[mt][nt][1]);
             }
@@ -468,14 +477,21 @@ hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q
 }
 
 // ------------------------------------------------------------------ force table pack
-// Per-row scale: the power of two at or above the row's largest |entry| (1
-// for an all-zero row), so that every row enters FP16 with magnitude <= 1 and
-// small rows keep their own relative precision; power-of-two scaling is exact.
+// Row information for the force: rinfo[r] = (Re psi(r, 0), Im psi(r, 0), scale,
+// 0) for r < R, zero for the padding rows up to a whole quad.  scale is the
+// power of two at or above the row's largest |entry| (1 for an all-zero row),
+// so that every row enters FP16 with magnitude <= 1 and small rows keep their
+// own relative precision; power-of-two scaling is exact.
 __global__ void __launch_bounds__(256)
-k_row_scale(const float *__restrict__ ftab, int n, int R, int nzp, float *__restrict__ rs)
+k_row_info(const float *__restrict__ ftab, const float *__restrict__ psi0, int n, int R, int Rq,
+           int nzp, float4 *__restrict__ rinfo)
 {
     const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= R) return;
+    if (r >= Rq) return;
+    if (r >= R) {
+        rinfo[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
     float m = 0.f;
     const float *f = ftab + (int64_t)r * nzp * 8;
     for (int i = 0; i < n * 8; ++i) m = fmaxf(m, fabsf(f[i]));
@@ -483,7 +499,7 @@ k_row_scale(const float *__restrict__ ftab, int n, int R, int nzp, float *__rest
     if (m > 0.f) {
         frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
     }
-    rs[r] = m > 0.f ? ldexpf(1.0f, e) : 1.0f;
+    rinfo[r] = make_float4(psi0[2 * r], psi0[2 * r + 1], m > 0.f ? ldexpf(1.0f, e) : 1.0f, 0.f);
 }
 
 // W fragments: wf[t][s][h][lane][8] halves, t = row quad (rows 4t..4t+3),
@@ -491,7 +507,7 @@ k_row_scale(const float *__restrict__ ftab, int n, int R, int nzp, float *__rest
 // component m % 4; K index k = 32 s + 8 (l/16) + i -> cos (k < nzk) or sin of
 // n_z = (k mod nzk) + 1.
 __global__ void __launch_bounds__(256)
-k_force_pack(const float *__restrict__ ftab, const float *__restrict__ rs, int n, int R, int nzp,
+k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, int n, int R, int nzp,
              int nzk, int quads, int ks, _Float16 *__restrict__ wf)
 {
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -504,7 +520,7 @@ k_force_pack(const float *__restrict__ ftab, const float *__restrict__ rs, int n
     const int m = lane & 15;
     const int r = 4 * t + (m >> 2);
     const int e = m & 3;
-    const float inv = r < R ? 1.0f / rs[r] : 1.0f;
+    const float inv = r < R ? 1.0f / rinfo[r].z : 1.0f;
     _Float16 hi[8], lo[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -532,54 +548,73 @@ k_force_pack(const float *__restrict__ ftab, const float *__restrict__ rs, int n
     }
 }
 
-hipError_t launch_force_pack(hipStream_t s, const float *ftab, const Geom &g, float *rowscale,
-                             _Float16 *wf)
+size_t force_rowinfo_bytes(const Geom &g) { return (size_t)(g.R + 3) / 4 * 4 * sizeof(float4); }
+
+hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0, const Geom &g,
+                             float4 *rinfo, _Float16 *wf)
 {
-    hipLaunchKernelGGL(k_row_scale, dim3((g.R + 255) / 256), dim3(256), 0, s, ftab, g.n, g.R, g.nzp,
-                       rowscale);
     const int quads = (g.R + 3) / 4;
+    hipLaunchKernelGGL(k_row_info, dim3((4 * quads + 255) / 256), dim3(256), 0, s, ftab, psi0, g.n,
+                       g.R, 4 * quads, g.nzp, rinfo);
     const int nzk = (g.n + 15) / 16 * 16;
     const int ks = nzk / 16;
     const int64_t total = (int64_t)quads * ks * 64;
     hipLaunchKernelGGL(k_force_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ftab,
-                       rowscale, g.n, g.R, g.nzp, nzk, quads, ks, wf);
+                       rinfo, g.n, g.R, g.nzp, nzk, quads, ks, wf);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ force
-// Block = 4 waves x 64 particles (NT = 4 N tiles of 16 particles per wave).
-// The W fragments of kForceTM row quads at a time are copied into LDS for the
-// whole block with direct global-to-LDS loads, double buffered: the next
-// quads' fragments stream in while the current ones are multiplied, one
-// barrier per kForceTM quads.  Every wave keeps its particles' CS fragments
-// in registers.  The lane group g = l/16 handles row 4t + g of each quad t, so
-// the four groups sum disjoint rows of the same particles and are combined at
-// the end.  Per-quad sums are FP32 and are added into FP64 once per kForceTM quads.
-constexpr int kForceTM = 4;
+// Block = 8 waves x 32 particles (NT = 2 N tiles of 16 particles per wave).
+// The W fragments and row information of kForceTM row quads at a time are
+// copied into LDS for the whole block with direct global-to-LDS loads, double
+// buffered in two separate LDS arrays: the next quads stream into one while
+// the current ones are multiplied out of the other, one barrier per kForceTM
+// quads.  (With the buffers as distinct objects the compiler can tell that
+// reads of the current one need not wait for the copies into the other.)
+// Every wave keeps its particles' CS fragments in registers.  The lane group
+// g = l/16 handles row 4t + g of each quad t, so the four groups sum disjoint
+// rows of the same particles and are combined at the end.  The matrix
+// products of quad t+1 are issued before the VALU epilogue of quad t.
+//
+// Phase g = exp(2 pi i (nx tx + ny ty)) of the lane's row: stepping 4 rows
+// multiplies it by e4 = cis(4 ty) within a line, or by
+// ew = e4 cis(tx - (2n+1) ty) when the step wraps into the next n_x line, so
+// every lane does the same work whichever line it is on.  Every
+// kForceAnchor stages all lanes re-anchor g exactly (FP64 sincos of the
+// exactly reduced phase) and add their FP32 sums into FP64.  PHI: also sum
+// the potential (only the diagnostics need it).
+constexpr int kForceTM = 8;
+constexpr int kForceAnchor = 2;
+constexpr int kForceWaves = 8;
+constexpr int kForceNT = 2;
+constexpr int kForceBlockParticles = kForceWaves * kForceNT * 16;
 
 // Copy pieces [0, npieces) of 64 half8 (1 KB) from src to LDS dst, piece p by
-// wave p % 4: lane l moves the 16 bytes at src[64 p + l] to dst[64 p + l].
+// wave p % kForceWaves: lane l moves the 16 bytes at src[64 p + l] to dst[64 p + l].
 __device__ inline void stage_w(const half8 *__restrict__ src, half8 *dst, int npieces, int wave,
                                int lane)
 {
-    for (int p = wave; p < npieces; p += 4)
+    for (int p = wave; p < npieces; p += kForceWaves)
         __builtin_amdgcn_global_load_lds(
             (const void *)(src + 64 * p + lane),
             (__attribute__((address_space(3))) void *)(dst + 64 * p), 16, 0, 0);
 }
 
-template <int KS>
-__global__ void __launch_bounds__(256)
+// keeps a value materialised in a VGPR in its current type
+__device__ inline void keep(float &x) { asm volatile("" : "+v"(x)); }
+
+template <int KS, bool PHI>
+__global__ void __launch_bounds__(512, 2)
 k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
              const double *__restrict__ m, double *__restrict__ vel, const _Float16 *__restrict__ wf,
-             const float *__restrict__ psi0, const float *__restrict__ rowscale, int n, int R,
-             int quads, double invL, int64_t N, double kick, double *__restrict__ F,
-             double *__restrict__ phi)
+             const float4 *__restrict__ rinfo, int n, int quads, double invL, int64_t N, double kick,
+             double *__restrict__ F, double *__restrict__ phi)
 {
-    constexpr int NT = 4;
-    constexpr int PIECES = kForceTM * KS * 2;  // 1 KB pieces per stage
-    extern __shared__ __align__(16) unsigned char smem[];
-    half8 *wl0 = reinterpret_cast<half8 *>(smem);  // [2][TM][KS][2][64]
+    constexpr int NT = kForceNT;
+    constexpr int PIECES = kForceTM * KS * 2;          // 1 KB W pieces per stage
+    constexpr int STAGE = PIECES * 64 + 4 * kForceTM;  // half8 per stage buffer (W, then row info)
+    __shared__ half8 wbuf0[STAGE], wbuf1[STAGE];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -589,18 +624,30 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
     const int nzk = 16 * KS;
     const int M = 2 * n + 1;
     const half8 *wsrc = reinterpret_cast<const half8 *>(wf);
+    const half8 *isrc = reinterpret_cast<const half8 *>(rinfo);
     const int nstage = (quads + kForceTM - 1) / kForceTM;
 
+    auto stage = [&](int st, half8 *dst) {
+        const int t0 = st * kForceTM;
+        const int cnt = quads - t0 < kForceTM ? quads - t0 : kForceTM;
+        stage_w(wsrc + (int64_t)t0 * KS * 2 * 64, dst, cnt * KS * 2, wave, lane);
+        if (wave == kForceWaves - 1 && lane < 4 * cnt)
+            __builtin_amdgcn_global_load_lds((const void *)(isrc + 4 * t0 + lane),
+                                             (__attribute__((address_space(3))) void *)(dst + PIECES * 64),
+                                             16, 0, 0);
+    };
     // first stage in flight while the particle fragments are formed
-    stage_w(wsrc, wl0, (quads < kForceTM ? quads : kForceTM) * KS * 2, wave, lane);
+    stage(0, wbuf0);
 
     half8 bh[NT][KS], bl[NT][KS];
     double tx[NT], ty[NT];
-    float gc[NT], gs[NT], e4c[NT], e4s[NT];
+    float gc[NT], gs[NT], e4c[NT], e4s[NT], ewc[NT], ews[NT];
     double fx[NT], fy[NT], fz[NT], fp[NT];
+    int nx, ny;
+    row_nxny(g, n, nx, ny);  // row g < 4 < R
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-        const int64_t j = (int64_t)blockIdx.x * 256 + wave * 64 + nt * 16 + ln;
+        const int64_t j = (int64_t)blockIdx.x * kForceBlockParticles + wave * (NT * 16) + nt * 16 + ln;
         const int64_t jc = j < N ? j : N - 1;
         tx[nt] = frac(pos[jc] * invL);
         ty[nt] = frac(pos[N + jc] * invL);
@@ -630,100 +677,106 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
         cis_turns(frac_mul(4, ty[nt]), a, b);
         e4c[nt] = (float)a;
         e4s[nt] = (float)b;
-        fx[nt] = fy[nt] = fz[nt] = fp[nt] = 0.0;
-    }
-    // lane group g starts at row g; rows advance by 4 with (nx, ny) tracked
-    // incrementally (a line n_x >= 0 ends at n_y = n, the next starts at -n)
-    int r = g;
-    int nx, ny;
-    row_nxny(r < R ? r : R - 1, n, nx, ny);
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        double a, b;
+        cis_turns(frac_lin(1, tx[nt], 4 - M, ty[nt]), a, b);
+        ewc[nt] = (float)a;
+        ews[nt] = (float)b;
+        keep(e4c[nt]);
+        keep(e4s[nt]);
+        keep(ewc[nt]);
+        keep(ews[nt]);
         cis_turns(frac_lin(nx, tx[nt], ny, ty[nt]), a, b);
         gc[nt] = (float)a;
         gs[nt] = (float)b;
+        fx[nt] = fy[nt] = fz[nt] = fp[nt] = 0.0;
     }
+    float sx[NT], sy[NT], sz[NT], sp[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) sx[nt] = sy[nt] = sz[nt] = sp[nt] = 0.f;
+    float fnx = (float)nx, fny = (float)ny;
+    const float fn = (float)n, fM = (float)M;
 
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    for (int st = 0; st < nstage; ++st) {
-        const int t0 = st * kForceTM;
-        const int tcnt = quads - t0 < kForceTM ? quads - t0 : kForceTM;
-        const half8 *wl = wl0 + (st & 1) * PIECES * 64;
-        if (st + 1 < nstage) {
-            const int t1 = t0 + kForceTM;
-            const int c1 = quads - t1 < kForceTM ? quads - t1 : kForceTM;
-            stage_w(wsrc + (int64_t)t1 * KS * 2 * 64, wl0 + ((st + 1) & 1) * PIECES * 64, c1 * KS * 2,
-                    wave, lane);
-        }
-        float sx[NT], sy[NT], sz[NT], sp[NT];
+    auto products = [&](const half8 *wl, int tt, f32x4 (&acc)[NT]) {
+        half8 ah[KS], al[KS];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) sx[nt] = sy[nt] = sz[nt] = sp[nt] = 0.f;
-        for (int tt = 0; tt < tcnt; ++tt) {
-            half8 ah[KS], al[KS];
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                ah[s] = wl[((tt * KS + s) * 2 + 0) * 64 + lane];
-                al[s] = wl[((tt * KS + s) * 2 + 1) * 64 + lane];
-            }
-            const bool rv = r < R;
-            float p0r = 0.f, p0i = 0.f, wscale = 0.f;
-            if (rv) {
-                p0r = psi0[2 * r];
-                p0i = psi0[2 * r + 1];
-                wscale = rowscale[r];
-            }
-            const float fnx = (float)nx, fny = (float)ny;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < KS; ++s) acc = mfma_split(ah[s], al[s], bh[nt][s], bl[nt][s], acc);
-                const float u0r = fmaf(acc[0], wscale, p0r), u0i = fmaf(acc[1], wscale, p0i);
-                const float u1r = acc[2] * wscale, u1i = acc[3] * wscale;
-                const float im0 = gc[nt] * u0i + gs[nt] * u0r;
-                const float re0 = gc[nt] * u0r - gs[nt] * u0i;
-                const float im1 = gc[nt] * u1i + gs[nt] * u1r;
-                sx[nt] = fmaf(fnx, im0, sx[nt]);
-                sy[nt] = fmaf(fny, im0, sy[nt]);
-                sz[nt] += im1;
-                sp[nt] += re0;
-            }
-            // next row of this lane group: r + 4
-            r += 4;
-            ny += 4;
-            if (ny <= n) {
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    const float c = gc[nt] * e4c[nt] - gs[nt] * e4s[nt];
-                    gs[nt] = gs[nt] * e4c[nt] + gc[nt] * e4s[nt];
-                    gc[nt] = c;
-                }
-            } else {
-                while (ny > n) {
-                    ny -= M;
-                    ++nx;
-                }
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    double a, b;
-                    cis_turns(frac_lin(nx, tx[nt], ny, ty[nt]), a, b);
-                    gc[nt] = (float)a;
-                    gs[nt] = (float)b;
-                }
-            }
+        for (int s = 0; s < KS; ++s) {
+            ah[s] = wl[((tt * KS + s) * 2 + 0) * 64 + lane];
+            al[s] = wl[((tt * KS + s) * 2 + 1) * 64 + lane];
         }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            fx[nt] += (double)sx[nt];
-            fy[nt] += (double)sy[nt];
-            fz[nt] += (double)sz[nt];
-            fp[nt] += (double)sp[nt];
+            acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) acc[nt] = mfma_split(ah[s], al[s], bh[nt][s], bl[nt][s], acc[nt]);
+        }
+    };
+    auto epilogue = [&](const float4 *ri, int tt, const f32x4 (&acc)[NT]) {
+        const float4 inf = ri[4 * tt + g];  // psi(r, 0), scale (zero past the last row)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const float u0r = fmaf(acc[nt][0], inf.z, inf.x), u0i = fmaf(acc[nt][1], inf.z, inf.y);
+            const float u1r = acc[nt][2] * inf.z, u1i = acc[nt][3] * inf.z;
+            const float im0 = gc[nt] * u0i + gs[nt] * u0r;
+            const float im1 = gc[nt] * u1i + gs[nt] * u1r;
+            sx[nt] = fmaf(fnx, im0, sx[nt]);
+            sy[nt] = fmaf(fny, im0, sy[nt]);
+            sz[nt] += im1;
+            if (PHI) sp[nt] += gc[nt] * u0r - gs[nt] * u0i;
+        }
+        // next row of this lane group: r + 4, possibly into the next n_x line
+        fny += 4.f;
+        const bool wrap = fny > fn;
+        if (wrap) {
+            fny -= fM;
+            fnx += 1.f;
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const float mc = wrap ? ewc[nt] : e4c[nt], ms = wrap ? ews[nt] : e4s[nt];
+            const float c = gc[nt] * mc - gs[nt] * ms;
+            gs[nt] = gs[nt] * mc + gc[nt] * ms;
+            gc[nt] = c;
+        }
+    };
+    auto run_stage = [&](int st, const half8 *wl, half8 *next) {
+        const int t0 = st * kForceTM;
+        const int tcnt = quads - t0 < kForceTM ? quads - t0 : kForceTM;
+        const float4 *ri = reinterpret_cast<const float4 *>(wl + PIECES * 64);
+        if (st + 1 < nstage) stage(st + 1, next);
+        f32x4 accA[NT], accB[NT];
+        products(wl, 0, accA);
+        for (int tt = 0; tt < tcnt; tt += 2) {
+            if (tt + 1 < tcnt) products(wl, tt + 1, accB);
+            epilogue(ri, tt, accA);
+            if (tt + 1 >= tcnt) break;
+            if (tt + 2 < tcnt) products(wl, tt + 2, accA);
+            epilogue(ri, tt + 1, accB);
+        }
+        if ((st + 1) % kForceAnchor == 0 || st + 1 == nstage) {
+            nx = (int)fnx;
+            ny = (int)fny;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                fx[nt] += (double)sx[nt];
+                fy[nt] += (double)sy[nt];
+                fz[nt] += (double)sz[nt];
+                if (PHI) fp[nt] += (double)sp[nt];
+                sx[nt] = sy[nt] = sz[nt] = sp[nt] = 0.f;
+                double a, b;
+                cis_turns(frac_lin(nx, tx[nt], ny, ty[nt]), a, b);
+                gc[nt] = (float)a;
+                gs[nt] = (float)b;
+            }
         }
         // the next stage's copies have landed, and every wave is done with this one
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+    };
+
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int st = 0; st < nstage; st += 2) {
+        run_stage(st, wbuf0, wbuf1);
+        if (st + 1 < nstage) run_stage(st + 1, wbuf1, wbuf0);
     }
     // combine the four lane groups (same particles, disjoint rows)
 #pragma unroll
@@ -732,9 +785,9 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
             fx[nt] += __shfl_xor(fx[nt], o, 64);
             fy[nt] += __shfl_xor(fy[nt], o, 64);
             fz[nt] += __shfl_xor(fz[nt], o, 64);
-            fp[nt] += __shfl_xor(fp[nt], o, 64);
+            if (PHI) fp[nt] += __shfl_xor(fp[nt], o, 64);
         }
-        const int64_t j = (int64_t)blockIdx.x * 256 + wave * 64 + nt * 16 + ln;
+        const int64_t j = (int64_t)blockIdx.x * kForceBlockParticles + wave * (NT * 16) + nt * 16 + ln;
         if (g == 0 && j < N) {
             const double f = 2.0 * q[j] * (6.283185307179586476925286766559 * invL);
             const double Fx = f * fx[nt], Fy = f * fy[nt], Fz = f * fz[nt];
@@ -743,7 +796,7 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
                 F[N + j] = Fy;
                 F[2 * N + j] = Fz;
             }
-            if (phi) phi[j] = 2.0 * fp[nt];
+            if (PHI) phi[j] = 2.0 * fp[nt];
             if (kick != 0.0) {
                 const double a = kick / m[j];
                 vel[j] += a * Fx;
@@ -754,32 +807,33 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
     }
 }
 
+template <int KS>
+static void launch_force_ks(hipStream_t s, dim3 grid, dim3 block, const double *pos, const double *q,
+                            const double *m, double *vel, const _Float16 *wf, const float4 *rinfo,
+                            int n, int quads, double invL, int64_t N, double kick, double *F,
+                            double *phi)
+{
+    if (phi)
+        hipLaunchKernelGGL((k_force_mfma<KS, true>), grid, block, 0, s, pos, q, m, vel, wf, rinfo, n,
+                           quads, invL, N, kick, F, phi);
+    else
+        hipLaunchKernelGGL((k_force_mfma<KS, false>), grid, block, 0, s, pos, q, m, vel, wf, rinfo, n,
+                           quads, invL, N, kick, F, phi);
+}
+
 hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, const double *m,
-                             double *vel, const _Float16 *wf, const float *psi0, const float *rowscale,
-                             const Geom &g, double L, int64_t N, double kick, double *F,
-                             double *phi)
+                             double *vel, const _Float16 *wf, const float4 *rinfo, const Geom &g,
+                             double L, int64_t N, double kick, double *F, double *phi)
 {
     const int quads = (g.R + 3) / 4;
     const int ks = (g.n + 15) / 16;
-    const int64_t blocks = (N + 255) / 256;
-    const size_t lds = (size_t)2 * kForceTM * ks * 2 * 64 * sizeof(half8);
+    const int64_t blocks = (N + kForceBlockParticles - 1) / kForceBlockParticles;
+    const dim3 grid((unsigned)blocks), block(64 * kForceWaves);
     switch (ks) {
-    case 1:
-        hipLaunchKernelGGL(k_force_mfma<1>, dim3((unsigned)blocks), dim3(256), lds, s, pos, q, m,
-                           vel, wf, psi0, rowscale, g.n, g.R, quads, 1.0 / L, N, kick, F, phi);
-        break;
-    case 2:
-        hipLaunchKernelGGL(k_force_mfma<2>, dim3((unsigned)blocks), dim3(256), lds, s, pos, q, m,
-                           vel, wf, psi0, rowscale, g.n, g.R, quads, 1.0 / L, N, kick, F, phi);
-        break;
-    case 3:
-        hipLaunchKernelGGL(k_force_mfma<3>, dim3((unsigned)blocks), dim3(256), lds, s, pos, q, m,
-                           vel, wf, psi0, rowscale, g.n, g.R, quads, 1.0 / L, N, kick, F, phi);
-        break;
-    default:
-        hipLaunchKernelGGL(k_force_mfma<4>, dim3((unsigned)blocks), dim3(256), lds, s, pos, q, m,
-                           vel, wf, psi0, rowscale, g.n, g.R, quads, 1.0 / L, N, kick, F, phi);
-        break;
+    case 1: launch_force_ks<1>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, quads, 1.0 / L, N, kick, F, phi); break;
+    case 2: launch_force_ks<2>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, quads, 1.0 / L, N, kick, F, phi); break;
+    case 3: launch_force_ks<3>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, quads, 1.0 / L, N, kick, F, phi); break;
+    default: launch_force_ks<4>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, quads, 1.0 / L, N, kick, F, phi); break;
     }
     return hipGetLastError();
 }

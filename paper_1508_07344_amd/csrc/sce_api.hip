@@ -64,7 +64,8 @@ struct sce_ctx_s {
     double *dout = nullptr;
 
     bool fields_valid = false;  // rho/psi/W/ftab correspond to the current positions
-    bool force_valid = false;   // F/phi correspond to the current positions
+    bool force_valid = false;   // F corresponds to the current positions
+    bool phi_valid = false;     // phi too (the split force leaves it out unless asked)
     int64_t step = 0;
     double time = 0.0;
     double q2sum = 0.0;
@@ -205,7 +206,7 @@ sce_status alloc_prec_buffers(sce_ctx c)
     free_devp(c->wscr);
     if (c->prec == SCE_PREC_SPLIT_F16) {
         HIPCHK(c, hipMalloc(&c->wf, sce::force_pack_bytes(c->g)));
-        HIPCHK(c, dev_alloc(c->wscr, (size_t)c->g.R * sizeof(float)));
+        HIPCHK(c, dev_alloc(c->wscr, sce::force_rowinfo_bytes(c->g)));
     }
     return SCE_OK;
 }
@@ -303,6 +304,7 @@ sce_status run_force(sce_ctx c, double kick)
         c->ev_frc.push_back(ep);
     }
     c->force_valid = true;
+    c->phi_valid = true;
     return SCE_OK;
 }
 
@@ -335,13 +337,13 @@ sce_status run_deposit_split(sce_ctx c)
     HIPCHK(c, sce::launch_reduce_solve<float>(c->stream, c->part, pl.splits, g, c->Stab, c->Gtab,
                                               c->Ktab, c->rho, c->psi, (float *)c->ftab,
                                               (float *)c->psi0, c->wpart, &c->wblocks));
-    HIPCHK(c, sce::launch_force_pack(c->stream, (const float *)c->ftab, g, c->wscr,
-                                     (_Float16 *)c->wf));
+    HIPCHK(c, sce::launch_force_pack(c->stream, (const float *)c->ftab, (const float *)c->psi0, g,
+                                     reinterpret_cast<float4 *>(c->wscr), (_Float16 *)c->wf));
     c->fields_valid = true;
     return SCE_OK;
 }
 
-sce_status run_force_split(sce_ctx c, double kick)
+sce_status run_force_split(sce_ctx c, double kick, bool want_phi)
 {
     EventPair ep{nullptr, nullptr};
     if (c->timing) {
@@ -350,13 +352,14 @@ sce_status run_force_split(sce_ctx c, double kick)
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
     HIPCHK(c, sce::launch_force_mfma(c->stream, c->pos, c->q, c->m, c->vel, (const _Float16 *)c->wf,
-                                     (const float *)c->psi0, c->wscr, c->g, c->L, c->N, kick, c->F,
-                                     c->phi));
+                                     reinterpret_cast<const float4 *>(c->wscr), c->g, c->L, c->N,
+                                     kick, c->F, want_phi ? c->phi : nullptr));
     if (c->timing && ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_frc.push_back(ep);
     }
     c->force_valid = true;
+    c->phi_valid = want_phi;
     return SCE_OK;
 }
 
@@ -368,20 +371,21 @@ sce_status deposit(sce_ctx c)
     return fail(c, SCE_ENOTSUP, "precision not available");
 }
 
-sce_status force(sce_ctx c, double kick)
+sce_status force(sce_ctx c, double kick, bool want_phi)
 {
     if (c->prec == SCE_PREC_FP64) return run_force<double>(c, kick);
     if (c->prec == SCE_PREC_FP32) return run_force<float>(c, kick);
-    if (c->prec == SCE_PREC_SPLIT_F16) return run_force_split(c, kick);
+    if (c->prec == SCE_PREC_SPLIT_F16) return run_force_split(c, kick, want_phi);
     return fail(c, SCE_ENOTSUP, "precision not available");
 }
 
-// One pass of the hot path at the current positions: deposit, solve, force (+kick).
-sce_status pass(sce_ctx c, double kick)
+// One pass of the hot path at the current positions: deposit, solve, force
+// (+kick); the potential at the particles too when want_phi.
+sce_status pass(sce_ctx c, double kick, bool want_phi = false)
 {
     sce_status st = deposit(c);
     if (st) return st;
-    return force(c, kick);
+    return force(c, kick, want_phi);
 }
 
 sce_status check_ready(sce_ctx c)
@@ -631,7 +635,7 @@ sce_status sce_diagnostics(sce_ctx c, sce_diag *out, double *rho_abs)
     if (st) return st;
     if (!out) return fail(c, SCE_EINVAL, "NULL output");
     if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
-    if (!(c->force_valid && c->fields_valid) && (st = pass(c, 0.0))) return st;
+    if (!(c->force_valid && c->fields_valid && c->phi_valid) && (st = pass(c, 0.0, true))) return st;
     const int nb = (int)((c->N + 255) / 256);
     void *ds = c->dscratch;
     st = ensure_bytes(c, ds, c->dscratch_bytes, (size_t)nb * 6 * sizeof(double));

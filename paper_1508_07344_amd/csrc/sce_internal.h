@@ -111,14 +111,15 @@ hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q
                                const Geom &g, double L, const MfmaDepositPlan &pl, double qscale,
                                float *rec, double *part);
 // Pack the FP32 force table into FP16 hi/lo matrix-core fragments, each row
-// scaled by its power-of-two scale rowscale[r] (R floats, written here).
+// scaled by its power-of-two scale; rinfo (force_rowinfo_bytes) receives per
+// row (Re psi(r,0), Im psi(r,0), scale, 0).
 size_t force_pack_bytes(const Geom &g);
-hipError_t launch_force_pack(hipStream_t s, const float *ftab, const Geom &g, float *rowscale,
-                             _Float16 *wf);
+size_t force_rowinfo_bytes(const Geom &g);
+hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0, const Geom &g,
+                             float4 *rinfo, _Float16 *wf);
 hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, const double *m,
-                             double *vel, const _Float16 *wf, const float *psi0, const float *rowscale,
-                             const Geom &g, double L, int64_t N, double kick, double *F,
-                             double *phi);
+                             double *vel, const _Float16 *wf, const float4 *rinfo, const Geom &g,
+                             double L, int64_t N, double kick, double *F, double *phi);
 
 // v += a F/m (if a != 0); x = wrap(x + b v) (if b != 0).
 hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *F,
