@@ -81,7 +81,6 @@ __device__ inline uint32_t feistel_perm(uint32_t i, uint32_t N, int h)
 // visited in the pseudo-random order of feistel_perm.  Per chunk of 32 particles:
 // the block builds per-particle tables in LDS (a = q cis(-nx tx) / qscale,
 // b = cis(-k ty), CS hi/lo), then every lane forms its own H fragment.
-constexpr int kDepRowsPerBlock = 256;
 constexpr int kDepChunk = 32;
 // Both deposit operands are multiplied by 7/8 before the split (and the
 // result by 64/49 in FP64).  Unscaled, cos(n_z theta) and h crowd just below
@@ -161,22 +160,31 @@ __host__ __device__ inline size_t dep_buf_bytes(int n, int MT)
                sizeof(float2);
 }
 
-// Block = 8 waves = 256 rows (two 16-row N tiles per wave), all CS rows
-// (MT tiles of 16); blockIdx.y = particle split, visited in the pseudo-random
-// order of the particle records.  Per chunk of 32 particles the block builds
-// LDS tables from the records: a = q cis(-k tx) for k = 0..n, b = cis(-k ty)
-// for k = -n..n (FP32), and the CS operand as FP16 hi/lo.  Tables are double
-// buffered: while every wave multiplies chunk c out of one buffer, the next
-// chunk's tables go into the other, so one barrier per chunk suffices.  Each
-// lane forms its own H = a b fragment (8 particles x 1 row), splits it into
-// hi/lo and adds its n_z = 0 contribution on the VALU.
+// Block = kDepCompW matrix-core waves + kDepBuildW table-builder waves.
+// blockIdx.y = particle split, visited in the pseudo-random order of the
+// particle records; the block's rows are 16 NTW rows per matrix-core wave.
+// Per chunk of 32 particles the builder waves write the LDS tables of the
+// next chunk from the records: a = q cis(-k tx) for k = 0..n, b = cis(-k ty)
+// for k = -n..n (FP32), and the CS operand as FP16 hi/lo, while the
+// matrix-core waves multiply the current chunk out of the other buffer; one
+// barrier per chunk.  Each matrix-core lane forms its own H = a b fragment (8
+// particles x 1 row), splits it into hi/lo and adds its n_z = 0 contribution
+// on the VALU.
+constexpr int kDepCompW = 12;
+constexpr int kDepBuildW = 4;
+constexpr int kDepThreads = 64 * (kDepCompW + kDepBuildW);
+
+__host__ __device__ inline int dep_ntw(int MT) { return MT <= 4 ? 2 : 1; }
+__host__ __device__ inline int dep_rows_per_block(int MT) { return 16 * dep_ntw(MT) * kDepCompW; }
+
 template <int MT>
-__global__ void __launch_bounds__(512, 2)
+__global__ void __launch_bounds__(kDepThreads)
 k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                int64_t per_split, double unscale_mf, double unscale_dc, double *__restrict__ part)
 {
     typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
     typedef float float2_t __attribute__((ext_vector_type(2)));
+    constexpr int NTW = MT <= 4 ? 2 : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int n1 = n + 1, M = 2 * n + 1;
     constexpr int CSR = MT * 16;
@@ -192,134 +200,129 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int g = lane >> 4;   // lane group: particles 8g..8g+7 of a chunk
-    const int ln = lane & 15;  // row within an N tile
     const int64_t j0 = (int64_t)blockIdx.y * per_split;
     const int64_t j1 = j0 + per_split < N ? j0 + per_split : N;
     const int64_t nchunks = (j1 - j0 + kDepChunk - 1) / kDepChunk;
     const int nb = (n1 + 7) / 8;
-    const int rf = dep_rec_floats(n);
 
-    for (int idx = tid; idx < (CSR - 2 * n) * kCSP; idx += 512)
+    for (int idx = tid; idx < (CSR - 2 * n) * kCSP; idx += kDepThreads)
         for (int b = 0; b < 2; ++b) {
             cs_hi(b)[2 * n * kCSP + idx] = (_Float16)0.0f;
             cs_lo(b)[2 * n * kCSP + idx] = (_Float16)0.0f;
         }
 
-    int rnx[2], rnyo[2];
-    bool rok[2];
+    if (wave >= kDepCompW) {
+        // ---------------- table builders
+        // tasks (axis d, block of 8 powers blk, particle p), particle fastest;
+        // builder thread bt owns tasks bt, bt + 64 kDepBuildW, ...
+        const int bt = tid - 64 * kDepCompW;
+        const int ntask = 3 * nb * kDepChunk;
+        const int rf = dep_rec_floats(n);
+        auto build_chunk = [&](int64_t c) {
+            const int b = (int)(c & 1);
+            const float csg = ((c >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
+            for (int task = bt; task < ntask; task += 64 * kDepBuildW) {
+                const int p = task & (kDepChunk - 1);
+                const int db = task / kDepChunk;
+                const int d = db / nb, blk = db - d * nb;
+                const int64_t j = j0 + c * kDepChunk + p;
+                float fc = 1.f, fs = 0.f, sc = 1.f, ss = 0.f, fq = 0.f;
+                if (j < j1) {
+                    const float *r0 = rec + j * rf;
+                    fc = r0[2 * (d * nb + blk)];
+                    fs = r0[2 * (d * nb + blk) + 1];
+                    sc = r0[2 * (3 * nb + d)];
+                    ss = r0[2 * (3 * nb + d) + 1];
+                    fq = r0[6 * (nb + 1)];
+                }
+                const int k0 = 8 * blk;
+                const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
+                if (d == 0) {
+                    float2 *dst = tab_a(b) + tab_row(p, n1, 4) + k0;
+                    for (int kk = 0; kk < kend; ++kk) {
+                        dst[kk] = make_float2(fq * fc, -fq * fs);
+                        const float t = fc * sc - fs * ss;
+                        fs = fc * ss + fs * sc;
+                        fc = t;
+                    }
+                } else if (d == 1) {
+                    float2 *dst = tab_b(b) + tab_row(p, M, padb) + n;
+                    for (int kk = 0; kk < kend; ++kk) {
+                        const int k = k0 + kk;
+                        dst[k] = make_float2(fc, -fs);
+                        dst[-k] = make_float2(fc, fs);
+                        const float t = fc * sc - fs * ss;
+                        fs = fc * ss + fs * sc;
+                        fc = t;
+                    }
+                } else {
+                    _Float16 *hi = cs_hi(b), *lo = cs_lo(b);
+                    for (int kk = 0; kk < kend; ++kk) {
+                        const int k = k0 + kk;
+                        if (k > 0) {
+                            _Float16 h, l;
+                            split_f16(csg * fc, h, l);
+                            hi[(k - 1) * kCSP + p] = h;
+                            lo[(k - 1) * kCSP + p] = l;
+                            split_f16(csg * fs, h, l);
+                            hi[(n + k - 1) * kCSP + p] = h;
+                            lo[(n + k - 1) * kCSP + p] = l;
+                        }
+                        const float t = fc * sc - fs * ss;
+                        fs = fc * ss + fs * sc;
+                        fc = t;
+                    }
+                }
+            }
+        };
+        build_chunk(0);
+        __syncthreads();
+        for (int64_t c = 0; c < nchunks; ++c) {
+            if (c + 1 < nchunks) build_chunk(c + 1);
+            __syncthreads();
+        }
+        return;
+    }
+
+    // ---------------- matrix-core waves
+    const int g = lane >> 4;   // lane group: particles 8g..8g+7 of a chunk
+    const int ln = lane & 15;  // row within an N tile
+    const int row0 = blockIdx.x * dep_rows_per_block(MT) + wave * 16 * NTW;
+    int rnx[NTW], rnyo[NTW];
+    bool rok[NTW];
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        const int r = blockIdx.x * kDepRowsPerBlock + wave * 32 + nt * 16 + ln;
+    for (int nt = 0; nt < NTW; ++nt) {
+        const int r = row0 + nt * 16 + ln;
         rok[nt] = r < R;
         int ny;
         row_nxny(r < R ? r : R - 1, n, rnx[nt], ny);
         rnyo[nt] = ny + n;  // column of k = ny in the b table
     }
 
-    f32x4 acc[MT][2][2];
+    f32x4 acc[MT][NTW][2];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) acc[mt][nt][0] = acc[mt][nt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float dc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
-    double dcd[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        for (int nt = 0; nt < NTW; ++nt) acc[mt][nt][0] = acc[mt][nt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // FP32 sums of the n_z = 0 row, added into this lane's FP64 slots in LDS
+    // (after the two table buffers) every 2^kDepDcLog chunks
+    float dc[NTW][2];
+    double *dcd = reinterpret_cast<double *>(smem + 2 * bufb) + (wave * NTW * 2) * 64 + lane;
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt) {
+        dc[nt][0] = dc[nt][1] = 0.f;
+        dcd[(2 * nt) * 64] = 0.0;
+        dcd[(2 * nt + 1) * 64] = 0.0;
+    }
 
-    // table tasks (axis d, block of 8 powers blk, particle p), particle fastest;
-    // thread tid owns tasks tid, tid + 512, ...; its first task's record
-    // fields are fetched one chunk ahead, further tasks (n_max >= 40) load theirs
-    const int ntask = 3 * nb * kDepChunk;
-    float pa_c, pa_s, ps_c, ps_s, pq;
-    auto load_task = [&](int task, int64_t c, float &fc, float &fs, float &sc, float &ss, float &fq) {
-        fc = 1.f;
-        fs = 0.f;
-        sc = 1.f;
-        ss = 0.f;
-        fq = 0.f;
-        const int p = task & (kDepChunk - 1);
-        const int db = task / kDepChunk;
-        const int d = db / nb, blk = db - d * nb;
-        const int64_t j = j0 + c * kDepChunk + p;
-        if (task < ntask && c < nchunks && j < j1) {
-            const float *r0 = rec + j * rf;
-            fc = r0[2 * (d * nb + blk)];
-            fs = r0[2 * (d * nb + blk) + 1];
-            sc = r0[2 * (3 * nb + d)];
-            ss = r0[2 * (3 * nb + d) + 1];
-            fq = r0[6 * (nb + 1)];
-        }
-    };
-    auto fetch = [&](int64_t c) { load_task(tid, c, pa_c, pa_s, ps_c, ps_s, pq); };
-    // tables of chunk c into buffer c & 1
-    auto build_task = [&](int task, int64_t c, float fc, float fs, float sc, float ss, float fq) {
-        const int b = (int)(c & 1);
-        const int p = task & (kDepChunk - 1);
-        const int db = task / kDepChunk;
-        const int d = db / nb, blk = db - d * nb;
-        const int k0 = 8 * blk;
-        const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
-        if (d == 0) {
-            float2 *dst = tab_a(b) + tab_row(p, n1, 4) + k0;
-            for (int kk = 0; kk < kend; ++kk) {
-                dst[kk] = make_float2(fq * fc, -fq * fs);
-                const float t = fc * sc - fs * ss;
-                fs = fc * ss + fs * sc;
-                fc = t;
-            }
-        } else if (d == 1) {
-            float2 *dst = tab_b(b) + tab_row(p, M, padb) + n;
-            for (int kk = 0; kk < kend; ++kk) {
-                const int k = k0 + kk;
-                dst[k] = make_float2(fc, -fs);
-                dst[-k] = make_float2(fc, fs);
-                const float t = fc * sc - fs * ss;
-                fs = fc * ss + fs * sc;
-                fc = t;
-            }
-        } else {
-            const float csg = ((c >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
-            _Float16 *hi = cs_hi(b), *lo = cs_lo(b);
-            for (int kk = 0; kk < kend; ++kk) {
-                const int k = k0 + kk;
-                if (k > 0) {
-                    _Float16 h, l;
-                    split_f16(csg * fc, h, l);
-                    hi[(k - 1) * kCSP + p] = h;
-                    lo[(k - 1) * kCSP + p] = l;
-                    split_f16(csg * fs, h, l);
-                    hi[(n + k - 1) * kCSP + p] = h;
-                    lo[(n + k - 1) * kCSP + p] = l;
-                }
-                const float t = fc * sc - fs * ss;
-                fs = fc * ss + fs * sc;
-                fc = t;
-            }
-        }
-    };
-    auto build = [&](int64_t c) {
-        if (tid < ntask) build_task(tid, c, pa_c, pa_s, ps_c, ps_s, pq);
-        for (int task = tid + 512; task < ntask; task += 512) {
-            float fc, fs, sc, ss, fq;
-            load_task(task, c, fc, fs, sc, ss, fq);
-            build_task(task, c, fc, fs, sc, ss, fq);
-        }
-    };
-
-    fetch(0);
-    build(0);
-    fetch(1);
-    __syncthreads();
+    __syncthreads();  // chunk 0's tables
     for (int64_t c = 0; c < nchunks; ++c) {
         const int b = (int)(c & 1);
-        if (c + 1 < nchunks) {
-            build(c + 1);
-            fetch(c + 2);
-        }
         if (c > 0 && (c & ((1 << kDepFlipLog) - 1)) == 0) {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < 2; ++nt) {
+                for (int nt = 0; nt < NTW; ++nt) {
                     acc[mt][nt][0] = -acc[mt][nt][0];
                     acc[mt][nt][1] = -acc[mt][nt][1];
                 }
@@ -327,7 +330,7 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
         const float2 *ta = tab_a(b), *tb = tab_b(b);
         const _Float16 *chi = cs_hi(b), *clo = cs_lo(b);
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
+        for (int nt = 0; nt < NTW; ++nt) {
             half8 bre_h, bre_l, bim_h, bim_l;
             float sre = 0.f, sim = 0.f;
 #pragma unroll
@@ -369,9 +372,9 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
         }
         if ((c & ((1 << kDepDcLog) - 1)) == ((1 << kDepDcLog) - 1)) {
 #pragma unroll
-            for (int nt = 0; nt < 2; ++nt) {
-                dcd[nt][0] += (double)dc[nt][0];
-                dcd[nt][1] += (double)dc[nt][1];
+            for (int nt = 0; nt < NTW; ++nt) {
+                dcd[(2 * nt) * 64] += (double)dc[nt][0];
+                dcd[(2 * nt + 1) * 64] += (double)dc[nt][1];
                 dc[nt][0] = dc[nt][1] = 0.f;
             }
         }
@@ -384,14 +387,14 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     const double outscale = unscale_mf * fsign;
     double *pb = part + (int64_t)blockIdx.y * (int64_t)n1 * 4 * Rpad;
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
+    for (int nt = 0; nt < NTW; ++nt) {
         // n_z = 0: the four lane groups' sums, added in a fixed order
-        double dre = dcd[nt][0] + (double)dc[nt][0], dim = dcd[nt][1] + (double)dc[nt][1];
+        double dre = dcd[(2 * nt) * 64] + (double)dc[nt][0], dim = dcd[(2 * nt + 1) * 64] + (double)dc[nt][1];
         dre += __shfl_xor(dre, 16, 64);
         dim += __shfl_xor(dim, 16, 64);
         dre += __shfl_xor(dre, 32, 64);
         dim += __shfl_xor(dim, 32, 64);
-        const int r = blockIdx.x * kDepRowsPerBlock + wave * 32 + nt * 16 + ln;
+        const int r = row0 + nt * 16 + ln;
         if (!rok[nt]) continue;
         if (g == 0) {
             pb[0 * Rpad + r] = unscale_dc * dre;
@@ -421,12 +424,17 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     }
 }
 
-size_t deposit_mfma_lds(int n) { return 2 * dep_buf_bytes(n, mfma_cs_tiles(n)); }
+size_t deposit_mfma_lds(int n)
+{
+    const int MT = mfma_cs_tiles(n);
+    return 2 * dep_buf_bytes(n, MT) + (size_t)kDepCompW * dep_ntw(MT) * 2 * 64 * sizeof(double);
+}
 
 MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
 {
     MfmaDepositPlan p;
-    p.row_blocks = (g.R + kDepRowsPerBlock - 1) / kDepRowsPerBlock;
+    const int rpb = dep_rows_per_block(mfma_cs_tiles(g.n));
+    p.row_blocks = (g.R + rpb - 1) / rpb;
     int64_t splits = (1024 + p.row_blocks - 1) / p.row_blocks;
     const int64_t max_splits = N / 512 > 1 ? N / 512 : 1;
     if (splits > max_splits) splits = max_splits;
@@ -447,7 +455,7 @@ static void launch_dep_mt(hipStream_t s, const float *rec, int64_t N, const Geom
                           const MfmaDepositPlan &pl, double unscale_mf, double unscale_dc,
                           double *part)
 {
-    hipLaunchKernelGGL(k_deposit_mfma<MT>, dim3(pl.row_blocks, pl.splits), dim3(512),
+    hipLaunchKernelGGL(k_deposit_mfma<MT>, dim3(pl.row_blocks, pl.splits), dim3(kDepThreads),
                        deposit_mfma_lds(g.n), s, rec, N, g.n, g.R, g.Rpad, pl.per_split,
                        unscale_mf, unscale_dc, part);
 }
