@@ -213,36 +213,60 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
 
     if (wave >= kDepCompW) {
         // ---------------- table builders
+        // raised issue priority: the next chunk's tables are the critical path,
+        // the matrix-core waves fill the remaining issue slots
+        __builtin_amdgcn_s_setprio(2);
         // tasks (axis d, block of 8 powers blk, particle p), particle fastest;
-        // builder thread bt owns tasks bt, bt + 64 kDepBuildW, ...
+        // builder thread bt owns tasks bt + s 64 kDepBuildW, s < kDepSlots.
+        // The record fields of the next chunk's tasks are loaded one chunk ahead.
+        constexpr int kDepSlots = 4;  // enough for n_max <= 64
         const int bt = tid - 64 * kDepCompW;
         const int ntask = 3 * nb * kDepChunk;
         const int rf = dep_rec_floats(n);
-        auto build_chunk = [&](int64_t c) {
-            const int b = (int)(c & 1);
-            const float csg = ((c >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
-            for (int task = bt; task < ntask; task += 64 * kDepBuildW) {
+        float rc[kDepSlots], rs[kDepSlots], sc[kDepSlots], ss[kDepSlots], rq[kDepSlots];
+        auto load_chunk = [&](int64_t c) {
+#pragma unroll
+            for (int sl = 0; sl < kDepSlots; ++sl) {
+                const int task = bt + sl * 64 * kDepBuildW;
                 const int p = task & (kDepChunk - 1);
                 const int db = task / kDepChunk;
                 const int d = db / nb, blk = db - d * nb;
                 const int64_t j = j0 + c * kDepChunk + p;
-                float fc = 1.f, fs = 0.f, sc = 1.f, ss = 0.f, fq = 0.f;
-                if (j < j1) {
+                rc[sl] = 1.f;
+                rs[sl] = 0.f;
+                sc[sl] = 1.f;
+                ss[sl] = 0.f;
+                rq[sl] = 0.f;
+                if (task < ntask && c < nchunks && j < j1) {
                     const float *r0 = rec + j * rf;
-                    fc = r0[2 * (d * nb + blk)];
-                    fs = r0[2 * (d * nb + blk) + 1];
-                    sc = r0[2 * (3 * nb + d)];
-                    ss = r0[2 * (3 * nb + d) + 1];
-                    fq = r0[6 * (nb + 1)];
+                    rc[sl] = r0[2 * (d * nb + blk)];
+                    rs[sl] = r0[2 * (d * nb + blk) + 1];
+                    sc[sl] = r0[2 * (3 * nb + d)];
+                    ss[sl] = r0[2 * (3 * nb + d) + 1];
+                    rq[sl] = r0[6 * (nb + 1)];
                 }
+            }
+        };
+        auto build_chunk = [&](int64_t c) {
+            const int b = (int)(c & 1);
+            const float csg = ((c >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
+#pragma unroll
+            for (int sl = 0; sl < kDepSlots; ++sl) {
+                const int task = bt + sl * 64 * kDepBuildW;
+                if (task >= ntask) continue;
+                const int p = task & (kDepChunk - 1);
+                const int db = task / kDepChunk;
+                const int d = db / nb, blk = db - d * nb;
+                float fc = rc[sl], fs = rs[sl];
+                const float c1 = sc[sl], s1 = ss[sl], fq = rq[sl];
                 const int k0 = 8 * blk;
                 const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
                 if (d == 0) {
                     float2 *dst = tab_a(b) + tab_row(p, n1, 4) + k0;
                     for (int kk = 0; kk < kend; ++kk) {
                         dst[kk] = make_float2(fq * fc, -fq * fs);
-                        const float t = fc * sc - fs * ss;
-                        fs = fc * ss + fs * sc;
+                        const float t = fc * c1 - fs * s1;
+                        fs = fc * s1 + fs * c1;
                         fc = t;
                     }
                 } else if (d == 1) {
@@ -251,8 +275,8 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                         const int k = k0 + kk;
                         dst[k] = make_float2(fc, -fs);
                         dst[-k] = make_float2(fc, fs);
-                        const float t = fc * sc - fs * ss;
-                        fs = fc * ss + fs * sc;
+                        const float t = fc * c1 - fs * s1;
+                        fs = fc * s1 + fs * c1;
                         fc = t;
                     }
                 } else {
@@ -268,17 +292,22 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                             hi[(n + k - 1) * kCSP + p] = h;
                             lo[(n + k - 1) * kCSP + p] = l;
                         }
-                        const float t = fc * sc - fs * ss;
-                        fs = fc * ss + fs * sc;
+                        const float t = fc * c1 - fs * s1;
+                        fs = fc * s1 + fs * c1;
                         fc = t;
                     }
                 }
             }
         };
+        load_chunk(0);
         build_chunk(0);
+        load_chunk(1);
         __syncthreads();
         for (int64_t c = 0; c < nchunks; ++c) {
-            if (c + 1 < nchunks) build_chunk(c + 1);
+            if (c + 1 < nchunks) {
+                build_chunk(c + 1);
+                load_chunk(c + 2);
+            }
             __syncthreads();
         }
         return;
