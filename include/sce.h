@@ -196,6 +196,8 @@ typedef struct {
     size_t hbm_budget_bytes;  /* device arena for resident requests; 0 = 4 GiB */
     int32_t precision;        /* SCE_PREC_FP32 or SCE_PREC_FP64 */
     int32_t max_active;       /* resident requests at most; 0 = 4096 */
+    int32_t no_graph;         /* 0: each tick replays a HIP graph of its launches, captured again
+                                 whenever the resident set changes; 1: launch directly */
     void *hip_stream;         /* hipStream_t, or NULL for a server-owned stream */
 } sce_server_opts;
 

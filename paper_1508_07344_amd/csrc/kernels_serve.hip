@@ -161,9 +161,10 @@ __device__ void dep_body(const ReqDesc &d, int idx, char *__restrict__ arena, ch
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_serve_deposit(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
-                const ServeItem *__restrict__ items)
+                const ServeItem *__restrict__ items, const int *__restrict__ counts)
 {
     extern __shared__ double smem_d[];
+    if ((int)blockIdx.x >= counts[0]) return;
     const ServeItem it = items[blockIdx.x];
     const ReqDesc &d = desc[it.slot];
     char *smem = reinterpret_cast<char *>(smem_d);
@@ -210,9 +211,10 @@ __device__ inline double blk_max(double v, double *sh)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_serve_reduce(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
-               const ServeItem *__restrict__ items)
+               const ServeItem *__restrict__ items, const int *__restrict__ counts)
 {
     __shared__ double sh[8];
+    if ((int)blockIdx.x >= counts[1]) return;
     const ServeItem it = items[blockIdx.x];
     const ReqDesc &d = desc[it.slot];
     const int n = d.n, R = d.R, nzs = d.nzs;
@@ -453,9 +455,11 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_serve_force(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
-              const char *__restrict__ tabs, const ServeItem *__restrict__ items)
+              const char *__restrict__ tabs, const ServeItem *__restrict__ items,
+              const int *__restrict__ counts)
 {
     __shared__ double shd[3 * 64 * 4];
+    if ((int)blockIdx.x >= counts[2]) return;
     const ServeItem it = items[blockIdx.x];
     const ReqDesc &d = desc[it.slot];
     if (d.nzs == 5)
@@ -471,8 +475,10 @@ k_serve_force(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
 // in order, a fixed shuffle tree adds the lanes; records the first and last
 // pass's diagnostics and counts the pass.
 __global__ void __launch_bounds__(64)
-k_serve_diag(ReqDesc *__restrict__ desc, char *__restrict__ arena, const int *__restrict__ slots)
+k_serve_diag(ReqDesc *__restrict__ desc, char *__restrict__ arena, const int *__restrict__ slots,
+             const int *__restrict__ counts)
 {
+    if ((int)blockIdx.x >= counts[3]) return;
     const int lane = threadIdx.x;
     ReqDesc &d = desc[slots[blockIdx.x]];
     const double *fpart = reinterpret_cast<const double *>(arena + d.o_fpart);
@@ -505,22 +511,25 @@ k_serve_diag(ReqDesc *__restrict__ desc, char *__restrict__ arena, const int *__
     d.pass = p + 1;
 }
 
+// Grids of gdep, gred, gfrc and gslots blocks (at least the counts on the
+// device, which blocks beyond return at once), so that a captured tick stays
+// valid while the resident set changes within the lists' capacity.
 template <typename T>
-hipError_t tick(hipStream_t s, const ReqDesc *desc, char *arena, const ServeItem *dep, int ndep,
-                const ServeItem *red, int nred, const ServeItem *frc, int nfrc, const int *slots,
-                int nslots)
+hipError_t tick(hipStream_t s, const ReqDesc *desc, char *arena, const ServeItem *dep, int gdep,
+                const ServeItem *red, int gred, const ServeItem *frc, int gfrc, const int *slots,
+                int gslots, const int *counts)
 {
     const size_t dep_lds = (size_t)3 * 64 * 17 * sizeof(typename Cx<T>::t) + 64 * sizeof(T);
-    if (ndep > 0)
-        hipLaunchKernelGGL(k_serve_deposit<T>, dim3(ndep), dim3(256), dep_lds, s, desc, arena, dep);
-    if (nred > 0)
-        hipLaunchKernelGGL(k_serve_reduce<T>, dim3(nred), dim3(256), 0, s, desc, arena, red);
-    if (nfrc > 0)
-        hipLaunchKernelGGL(k_serve_force<T>, dim3(nfrc), dim3(256), 0, s, desc, arena,
-                           (const char *)arena, frc);
-    if (nslots > 0)
-        hipLaunchKernelGGL(k_serve_diag, dim3(nslots), dim3(64), 0, s, const_cast<ReqDesc *>(desc),
-                           arena, slots);
+    if (gdep > 0)
+        hipLaunchKernelGGL(k_serve_deposit<T>, dim3(gdep), dim3(256), dep_lds, s, desc, arena, dep, counts);
+    if (gred > 0)
+        hipLaunchKernelGGL(k_serve_reduce<T>, dim3(gred), dim3(256), 0, s, desc, arena, red, counts);
+    if (gfrc > 0)
+        hipLaunchKernelGGL(k_serve_force<T>, dim3(gfrc), dim3(256), 0, s, desc, arena,
+                           (const char *)arena, frc, counts);
+    if (gslots > 0)
+        hipLaunchKernelGGL(k_serve_diag, dim3(gslots), dim3(64), 0, s, const_cast<ReqDesc *>(desc),
+                           arena, slots, counts);
     return hipGetLastError();
 }
 
@@ -564,11 +573,13 @@ size_t serve_layout(ReqDesc &d, int elem_bytes)
 }
 
 hipError_t launch_serve_tick(hipStream_t s, int elem_bytes, const ReqDesc *desc, char *arena,
-                             const ServeItem *dep, int ndep, const ServeItem *red, int nred,
-                             const ServeItem *frc, int nfrc, const int *slots, int nslots)
+                             const ServeItem *dep, int gdep, const ServeItem *red, int gred,
+                             const ServeItem *frc, int gfrc, const int *slots, int gslots,
+                             const int *counts)
 {
-    if (elem_bytes == 8) return tick<double>(s, desc, arena, dep, ndep, red, nred, frc, nfrc, slots, nslots);
-    return tick<float>(s, desc, arena, dep, ndep, red, nred, frc, nfrc, slots, nslots);
+    if (elem_bytes == 8)
+        return tick<double>(s, desc, arena, dep, gdep, red, gred, frc, gfrc, slots, gslots, counts);
+    return tick<float>(s, desc, arena, dep, gdep, red, gred, frc, gfrc, slots, gslots, counts);
 }
 
 }  // namespace sce

@@ -53,9 +53,12 @@ struct ServeItem {
 size_t serve_layout(ReqDesc &d, int elem_bytes);
 
 // One tick: deposit, reduce + solve, force + kick + drift, diagnostics.
-// T = float or double selects the working precision of phases and sums.
+// elem_bytes 4 or 8 selects the working precision of phases and sums.  The
+// grids have gdep, gred, gfrc and gslots blocks; counts (device, 4 ints)
+// holds the numbers of valid items of each list, blocks beyond return.
 hipError_t launch_serve_tick(hipStream_t s, int elem_bytes, const ReqDesc *desc, char *arena,
-                             const ServeItem *dep, int ndep, const ServeItem *red, int nred,
-                             const ServeItem *frc, int nfrc, const int *slots, int nslots);
+                             const ServeItem *dep, int gdep, const ServeItem *red, int gred,
+                             const ServeItem *frc, int gfrc, const int *slots, int gslots,
+                             const int *counts);
 
 }  // namespace sce

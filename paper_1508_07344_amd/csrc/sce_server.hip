@@ -164,9 +164,15 @@ struct sce_server_s {
     Mirrored<ReqDesc> desc;
     Mirrored<ServeItem> dep, red, frc;
     Mirrored<int> slots;
+    Mirrored<int> counts;    // ndep, nred, nfrc, nslots on the device
     Mirrored<double> stage;  // retirement staging
     int ndep = 0, nred = 0, nfrc = 0, nslots = 0;
     bool dirty = true;
+    // the tick's launches captured once per work list and replayed
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    size_t gcap[4] = {0, 0, 0, 0};  // list capacities the graph was captured with
 
     uint64_t next_id = 1;
     std::deque<std::unique_ptr<Request>> queue;
@@ -298,7 +304,55 @@ sce_status build_lists(sce_server s)
         SHIP(s, hipMemcpyAsync(s->frc.dev, s->frc.host, nf * sizeof(ServeItem), hipMemcpyHostToDevice, s->stream));
     if (is)
         SHIP(s, hipMemcpyAsync(s->slots.dev, s->slots.host, is * sizeof(int), hipMemcpyHostToDevice, s->stream));
+    SHIP(s, s->counts.reserve(4));
+    s->counts.host[0] = s->ndep;
+    s->counts.host[1] = s->nred;
+    s->counts.host[2] = s->nfrc;
+    s->counts.host[3] = s->nslots;
+    SHIP(s, hipMemcpyAsync(s->counts.dev, s->counts.host, 4 * sizeof(int), hipMemcpyHostToDevice, s->stream));
     s->dirty = false;
+    return SCE_OK;
+}
+
+void drop_graph(sce_server s)
+{
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+}
+
+// Launch one tick's kernels: replayed from a HIP graph whose grids cover the
+// work lists' capacities (blocks beyond the device-side counts return at
+// once), captured again only when a capacity grows; or launched directly with
+// exact grids.
+sce_status launch_tick(sce_server s)
+{
+    if (!s->use_graph) {
+        const hipError_t e = sce::launch_serve_tick(s->stream, s->elem, s->desc.dev, s->arena, s->dep.dev,
+                                                    s->ndep, s->red.dev, s->nred, s->frc.dev, s->nfrc,
+                                                    s->slots.dev, s->nslots, s->counts.dev);
+        return e == hipSuccess ? SCE_OK : shipfail(s, e, "launch_serve_tick");
+    }
+    const size_t cap[4] = {s->dep.cap, s->red.cap, s->frc.cap, s->slots.cap};
+    if (!s->gexec || std::memcmp(cap, s->gcap, sizeof(cap)) != 0) {
+        drop_graph(s);
+        SHIP(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t le = sce::launch_serve_tick(s->stream, s->elem, s->desc.dev, s->arena, s->dep.dev,
+                                                     (int)cap[0], s->red.dev, (int)cap[1], s->frc.dev,
+                                                     (int)cap[2], s->slots.dev, (int)cap[3], s->counts.dev);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(s->stream, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return shipfail(s, le, "launch_serve_tick (capture)");
+        }
+        SHIP(s, ce);
+        s->graph = g;
+        SHIP(s, hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+        std::memcpy(s->gcap, cap, sizeof(cap));
+    }
+    SHIP(s, hipGraphLaunch(s->gexec, s->stream));
     return SCE_OK;
 }
 
@@ -411,6 +465,7 @@ sce_status sce_server_create(const sce_server_opts *opts, sce_server *out)
     s->elem = o.precision == SCE_PREC_FP64 ? 8 : 4;
     s->arena_bytes = o.hbm_budget_bytes ? o.hbm_budget_bytes : ((size_t)4 << 30);
     s->max_slots = o.max_active ? o.max_active : 4096;
+    s->use_graph = o.no_graph == 0;
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) {
         if (o.hip_stream) {
@@ -496,9 +551,8 @@ sce_status sce_server_tick(sce_server s, int32_t *n_active, int32_t *n_queued)
         std::vector<Request *> fin;
         st = stage_finishing(s, fin);
         if (st != SCE_OK) return st;
-        SHIP(s, sce::launch_serve_tick(s->stream, s->elem, s->desc.dev, s->arena, s->dep.dev, s->ndep,
-                                       s->red.dev, s->nred, s->frc.dev, s->nfrc, s->slots.dev,
-                                       s->nslots));
+        st = launch_tick(s);
+        if (st != SCE_OK) return st;
         st = copy_finishing(s, fin);
         if (st != SCE_OK) return st;
         SHIP(s, hipStreamSynchronize(s->stream));
@@ -585,11 +639,13 @@ void sce_server_destroy(sce_server s)
     if (!s) return;
     (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graph(s);
     s->desc.release();
     s->dep.release();
     s->red.release();
     s->frc.release();
     s->slots.release();
+    s->counts.release();
     s->stage.release();
     if (s->arena) (void)hipFree(s->arena);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);

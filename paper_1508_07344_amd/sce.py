@@ -40,7 +40,8 @@ class _Diag(ctypes.Structure):
 
 class _ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("precision", ctypes.c_int32),
-                ("max_active", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+                ("max_active", ctypes.c_int32), ("no_graph", ctypes.c_int32),
+                ("hip_stream", ctypes.c_void_p)]
 
 
 class _Request(ctypes.Structure):
@@ -336,10 +337,11 @@ def _diag(d: _Diag) -> Diag:
 class Server:
     """Batched server of independent simulations (``sce_server``)."""
 
-    def __init__(self, hbm_budget_bytes: int = 0, precision: str = "fp32", max_active: int = 0):
+    def __init__(self, hbm_budget_bytes: int = 0, precision: str = "fp32", max_active: int = 0,
+                 graph: bool = True):
         lib = load_library()
         self._lib = lib
-        o = _ServerOpts(hbm_budget_bytes, PREC[precision], max_active, None)
+        o = _ServerOpts(hbm_budget_bytes, PREC[precision], max_active, 0 if graph else 1, None)
         h = ctypes.c_void_p()
         st = lib.sce_server_create(ctypes.byref(o), ctypes.byref(h))
         if st != SCE_OK:

@@ -75,7 +75,7 @@ def test_server_arguments_are_rejected_on_host():
     assert lib.sce_server_create(None, None) == sce.SCE_EINVAL
     for prec, max_active, want in [(sce.PREC["split_f16"], 0, sce.SCE_ENOTSUP), (7, 0, sce.SCE_ENOTSUP),
                                    (sce.PREC["fp32"], -1, sce.SCE_EINVAL)]:
-        o = _ServerOpts(0, prec, max_active, None)
+        o = _ServerOpts(0, prec, max_active, 0, None)
         assert lib.sce_server_create(ctypes.byref(o), ctypes.byref(h)) == want
         assert not h.value
     n = ctypes.c_int32()
