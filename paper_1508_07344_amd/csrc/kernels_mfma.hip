@@ -76,11 +76,7 @@ __device__ inline uint32_t feistel_perm(uint32_t i, uint32_t N, int h)
 }
 
 // ------------------------------------------------------------------ deposit
-// Block = 8 waves = 256 rows (two 16-row N tiles per wave), all CS rows
-// (MT tiles of 16).  blockIdx.y = particle split; the split's particles are
-// visited in the pseudo-random order of feistel_perm.  Per chunk of 32 particles:
-// the block builds per-particle tables in LDS (a = q cis(-nx tx) / qscale,
-// b = cis(-k ty), CS hi/lo), then every lane forms its own H fragment.
+// Particles are taken in chunks of 32 (the K depth of one matrix instruction).
 constexpr int kDepChunk = 32;
 // Both deposit operands are multiplied by 7/8 before the split (and the
 // result by 64/49 in FP64).  Unscaled, cos(n_z theta) and h crowd just below
@@ -160,9 +156,10 @@ __host__ __device__ inline size_t dep_buf_bytes(int n, int MT)
                sizeof(float2);
 }
 
-// Block = kDepCompW matrix-core waves + kDepBuildW table-builder waves.
-// blockIdx.y = particle split, visited in the pseudo-random order of the
-// particle records; the block's rows are 16 NTW rows per matrix-core wave.
+// Block = kDepCompW matrix-core waves + kDepBuildW table-builder waves for
+// one (row block, particle split) pair; the split's particles are visited in
+// the pseudo-random order of the particle records, and the block's rows are
+// 16 NTW rows per matrix-core wave.
 // Per chunk of 32 particles the builder waves write the LDS tables of the
 // next chunk from the records: a = q cis(-k tx) for k = 0..n, b = cis(-k ty)
 // for k = -n..n (FP32), and the CS operand as FP16 hi/lo, while the
@@ -177,11 +174,25 @@ constexpr int kDepThreads = 64 * (kDepCompW + kDepBuildW);
 __host__ __device__ inline int dep_ntw(int MT) { return MT <= 4 ? 2 : 1; }
 __host__ __device__ inline int dep_rows_per_block(int MT) { return 16 * dep_ntw(MT) * kDepCompW; }
 
+// XCD-aware block order: consecutive blocks go to different XCDs (each with
+// its own L2), so the grid is numbered such that the row blocks of one
+// particle split are dispatched to the same XCD one after another and their
+// reads of the split's particle records hit that XCD's L2.  Linear block L
+// runs on XCD L % 8; its position t = L / 8 in that XCD's sequence selects
+// row block t % row_blocks of split (t / row_blocks) * 8 + L % 8.
+constexpr int kXcds = 8;
+
 template <int MT>
 __global__ void __launch_bounds__(kDepThreads)
 k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
-               int64_t per_split, double unscale_mf, double unscale_dc, double *__restrict__ part)
+               int64_t per_split, int row_blocks, int splits, double unscale_mf, double unscale_dc,
+               double *__restrict__ part)
 {
+    const int blk_l = blockIdx.x;
+    const int blk_t = blk_l / kXcds;
+    const int rblk = blk_t % row_blocks;
+    const int split = (blk_t / row_blocks) * kXcds + blk_l % kXcds;
+    if (split >= splits) return;
     typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
     typedef float float2_t __attribute__((ext_vector_type(2)));
     constexpr int NTW = MT <= 4 ? 2 : 1;
@@ -200,7 +211,7 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t j0 = (int64_t)blockIdx.y * per_split;
+    const int64_t j0 = (int64_t)split * per_split;
     const int64_t j1 = j0 + per_split < N ? j0 + per_split : N;
     const int64_t nchunks = (j1 - j0 + kDepChunk - 1) / kDepChunk;
     const int nb = (n1 + 7) / 8;
@@ -316,7 +327,7 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     // ---------------- matrix-core waves
     const int g = lane >> 4;   // lane group: particles 8g..8g+7 of a chunk
     const int ln = lane & 15;  // row within an N tile
-    const int row0 = blockIdx.x * dep_rows_per_block(MT) + wave * 16 * NTW;
+    const int row0 = rblk * dep_rows_per_block(MT) + wave * 16 * NTW;
     int rnx[NTW], rnyo[NTW];
     bool rok[NTW];
 #pragma unroll
@@ -414,7 +425,7 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     const int64_t last = nchunks - 1;
     const double fsign = last >= 0 && ((last >> kDepFlipLog) & 1) ? -1.0 : 1.0;
     const double outscale = unscale_mf * fsign;
-    double *pb = part + (int64_t)blockIdx.y * (int64_t)n1 * 4 * Rpad;
+    double *pb = part + (int64_t)split * (int64_t)n1 * 4 * Rpad;
 #pragma unroll
     for (int nt = 0; nt < NTW; ++nt) {
         // n_z = 0: the four lane groups' sums, added in a fixed order
@@ -459,15 +470,33 @@ size_t deposit_mfma_lds(int n)
     return 2 * dep_buf_bytes(n, MT) + (size_t)kDepCompW * dep_ntw(MT) * 2 * 64 * sizeof(double);
 }
 
+// Particle splits: one block per (row block, split) holds a whole CU (16
+// waves, 96 KB of LDS at n_max = 32), so the grid runs in rounds of one block
+// per CU.  The split count is a multiple of kXcds (the XCD-aware numbering
+// needs whole groups) chosen to minimise rounds per particle, i.e. to avoid a
+// last round that is nearly empty; ties go to fewer splits (fewer partials).
 MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
 {
     MfmaDepositPlan p;
     const int rpb = dep_rows_per_block(mfma_cs_tiles(g.n));
     p.row_blocks = (g.R + rpb - 1) / rpb;
-    int64_t splits = (1024 + p.row_blocks - 1) / p.row_blocks;
-    const int64_t max_splits = N / 512 > 1 ? N / 512 : 1;
-    if (splits > max_splits) splits = max_splits;
-    if (splits < 1) splits = 1;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus < 1) cus = 256;
+    const int64_t smax = N / 512 >= kXcds ? (N / 512) / kXcds * kXcds : 0;
+    int64_t splits = N / 512 > 1 ? N / 512 : 1;  // small N: fewer splits than one XCD group
+    if (smax >= kXcds) {
+        double best = 1e300;
+        for (int64_t sp = kXcds; sp <= smax && sp <= 4096; sp += kXcds) {
+            const int64_t blocks = (int64_t)p.row_blocks * sp;
+            const double cost = (double)((blocks + cus - 1) / cus) / (double)sp;
+            if (cost < best * (1.0 - 1e-9)) {
+                best = cost;
+                splits = sp;
+            }
+        }
+    }
     int64_t per = (N + splits - 1) / splits;
     per = (per + kDepChunk - 1) / kDepChunk * kDepChunk;
     p.per_split = per;
@@ -484,9 +513,11 @@ static void launch_dep_mt(hipStream_t s, const float *rec, int64_t N, const Geom
                           const MfmaDepositPlan &pl, double unscale_mf, double unscale_dc,
                           double *part)
 {
-    hipLaunchKernelGGL(k_deposit_mfma<MT>, dim3(pl.row_blocks, pl.splits), dim3(kDepThreads),
+    // splits rounded up to whole groups of kXcds; blocks past the last split return
+    const int groups = (pl.splits + kXcds - 1) / kXcds;
+    hipLaunchKernelGGL(k_deposit_mfma<MT>, dim3(groups * kXcds * pl.row_blocks), dim3(kDepThreads),
                        deposit_mfma_lds(g.n), s, rec, N, g.n, g.R, g.Rpad, pl.per_split,
-                       unscale_mf, unscale_dc, part);
+                       pl.row_blocks, pl.splits, unscale_mf, unscale_dc, part);
 }
 
 size_t deposit_mfma_rec_bytes(int64_t N, int n) { return (size_t)N * dep_rec_floats(n) * sizeof(float); }
