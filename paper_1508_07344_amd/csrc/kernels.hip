@@ -316,13 +316,34 @@ DepositPlan plan_deposit(const Geom &g, int64_t N, int elem_bytes)
     // LDS chunk: keep the h tile at 32 KiB
     p.kc = (32768 / elem_bytes / 2) / p.rows_per_wg;
     if (p.kc < 4) p.kc = 4;
-    // enough blocks to fill 256 CUs several times over; at least 256 particles per split
+    // Splits: enough blocks to fill the CUs several times over, at least 256
+    // particles per split, and a block count that fills whole rounds of
+    // resident blocks (a nearly empty last round costs a full round).
     const int64_t blocks_per_split = (int64_t)p.row_blocks * p.grid_y;
-    int64_t splits = (2048 + blocks_per_split - 1) / blocks_per_split;
-    const int64_t max_splits = N / 256 > 1 ? N / 256 : 1;
-    if (splits > max_splits) splits = max_splits;
-    if (splits > 1024) splits = 1024;
-    if (splits < 1) splits = 1;
+    int64_t max_splits = N / 256 > 1 ? N / 256 : 1;
+    if (max_splits > 1024) max_splits = 1024;
+    int dev = 0, cus = 256, per_cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const size_t shmem = (size_t)p.kc * p.rows_per_wg * 2 * elem_bytes;
+    const void *kf = elem_bytes == 8
+                         ? (p.zb == 4 ? (const void *)k_deposit<double, 4> : (const void *)k_deposit<double, 8>)
+                         : (p.zb == 4 ? (const void *)k_deposit<float, 4> : (const void *)k_deposit<float, 8>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf, 256, shmem) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (cus < 1) cus = 256;
+    const int64_t slots = (int64_t)cus * per_cu;
+    int64_t splits = 1;
+    double best = 1e300;
+    for (int64_t sp = 1; sp <= max_splits; ++sp) {
+        const int64_t blocks = blocks_per_split * sp;
+        if (blocks < 2 * slots && sp < max_splits) continue;  // at least two rounds when possible
+        const double cost = (double)((blocks + slots - 1) / slots) / (double)sp;
+        if (cost < best * (1.0 - 1e-9)) {
+            best = cost;
+            splits = sp;
+        }
+    }
     int64_t per = (N + splits - 1) / splits;
     per = (per + p.kc - 1) / p.kc * p.kc;
     p.per_split = per;
