@@ -35,6 +35,24 @@ __device__ inline void split_f16(float x, _Float16 &hi, _Float16 &lo)
     lo = (_Float16)(x - (float)hi);
 }
 
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+
+// lo parts of two values whose hi parts (round to nearest) are packed in hi:
+// lo = fp16(x - hi), the difference formed exactly inside the mixed-precision
+// FMA and rounded once, as fp16(x - (float)hi) is (that difference is exact in
+// FP32).  Two instructions instead of two conversions back, two subtractions
+// and a packing conversion.
+__device__ inline half2_t split_lo2(float2_t x, half2_t hi)
+{
+    half2_t lo;
+    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "=&v"(lo)
+        : "v"(hi), "v"(x[0]), "v"(x[1]));
+    return lo;
+}
+
 __device__ inline f32x4 mfma16(half8 a, half8 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -89,8 +107,8 @@ constexpr float kDepOpScale = 0.875f;
 // the running sum is much larger than each increment, slightly toward -inf.
 // Over thousands of chunks that directional bias is identical in every
 // accumulator and would act like a spurious charge at the origin.  The running
-// sum therefore changes sign every 4 chunks (accumulator and CS operand
-// negated together), so the bias alternates direction and cancels.
+// sum therefore changes sign every 2^kDepFlipLog chunks (accumulator and CS
+// operand negated together), so the bias alternates direction and cancels.
 
 // Per-particle record in visiting order, FP32, for nb = ceil((n+1)/8) blocks
 // of 8 powers per axis: [d][blk] = cis(2 pi 8 blk t_d) (anchors, formed in
@@ -127,15 +145,34 @@ k_deposit_prep(const double *__restrict__ pos, const double *__restrict__ q, int
     o[6 * (nb + 1)] = (float)(q[j] * qfac);
 }
 
-// LDS table layouts of the deposit.  Row of particle p in the a table (n+1
-// entries): groups of 8 particles separated by 4 float2, so the four lane
-// groups (particles 8g..8g+7) start in different banks.  b table (2n+1
-// entries): the group padding makes the groups' rows start 128 bytes apart
+// LDS table layouts of the deposit.  Row strides are those of the largest
+// n_max of the tile class (8 MT), fixed at compile time, so that the
+// matrix-core waves address the 8 particles of their lane group with the
+// read instruction's immediate offset.  Row of particle p in the a table
+// (8 MT + 1 entries, k = 0..n used): groups of 8 particles separated by 4
+// float2, so the four lane groups (particles 8g..8g+7) start in different
+// banks.  b table (16 MT + 1 entries, k = -n..n used around column n): the
+// group padding of 8 float2 makes the groups' rows start 128 bytes apart
 // modulo the 256-byte bank cycle, so that lane groups 0/1 and 2/3, which read
 // 16 consecutive entries each in the same pass, use disjoint banks.  CS rows
 // hold 32 particles plus 8 halves of padding (80-byte stride), so that the 16
 // rows read by a lane group's 16-byte fragment loads fall in distinct banks.
-__host__ __device__ inline int tab_pad_b(int n) { return ((2 * n + 1) & 3) == 1 ? 8 : 24; }
+// A table entry read as a volatile LDS double, which the compiler keeps as a
+// read of its own.
+typedef const volatile double __attribute__((address_space(3))) lds_f2;
+__device__ inline float2 lds_read(lds_f2 *p)
+{
+    const double d = *p;
+    return __builtin_bit_cast(float2, d);
+}
+
+template <int MT>
+struct DepTab {
+    static constexpr int wa = 8 * MT + 1;
+    static constexpr int wb = 16 * MT + 1;
+    static constexpr int pada = 4;
+    static constexpr int padb = 8;  // wb = 1 mod 4
+};
 __device__ inline int tab_row(int p, int w, int pad) { return p * w + (p >> 3) * pad; }
 constexpr int kCSP = kDepChunk + 8;
 
@@ -149,11 +186,12 @@ constexpr int kDepDcLog = 4;
 // The n_z = 0 row (all ones) is summed on the VALU instead.
 __host__ __device__ inline int mfma_cs_tiles(int n) { return (2 * n + 15) / 16; }
 
-__host__ __device__ inline size_t dep_buf_bytes(int n, int MT)
+template <int MT>
+__host__ __device__ constexpr size_t dep_buf_bytes()
 {
+    using T = DepTab<MT>;
     return (size_t)MT * 16 * kCSP * 2 * sizeof(_Float16) +
-           (size_t)(kDepChunk * (n + 1) + 16 + kDepChunk * (2 * n + 1) + 4 * tab_pad_b(n)) *
-               sizeof(float2);
+           (size_t)(kDepChunk * T::wa + 4 * T::pada + kDepChunk * T::wb + 4 * T::padb) * sizeof(float2);
 }
 
 // Block = kDepCompW matrix-core waves + kDepBuildW table-builder waves for
@@ -193,20 +231,18 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     const int rblk = blk_t % row_blocks;
     const int split = (blk_t / row_blocks) * kXcds + blk_l % kXcds;
     if (split >= splits) return;
-    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-    typedef float float2_t __attribute__((ext_vector_type(2)));
     constexpr int NTW = MT <= 4 ? 2 : 1;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int n1 = n + 1, M = 2 * n + 1;
+    const int n1 = n + 1;
     constexpr int CSR = MT * 16;
-    const size_t bufb = dep_buf_bytes(n, MT);
+    constexpr size_t bufb = dep_buf_bytes<MT>();
+    using T = DepTab<MT>;
     auto cs_hi = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb); };
     auto cs_lo = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb) + CSR * kCSP; };
     auto tab_a = [&](int b) {
         return reinterpret_cast<float2 *>(smem + b * bufb + (size_t)CSR * kCSP * 2 * sizeof(_Float16));
     };
-    const int padb = tab_pad_b(n);
-    auto tab_b = [&](int b) { return tab_a(b) + kDepChunk * n1 + 16; };
+    auto tab_b = [&](int b) { return tab_a(b) + kDepChunk * T::wa + 4 * T::pada; };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -273,7 +309,7 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                 const int k0 = 8 * blk;
                 const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
                 if (d == 0) {
-                    float2 *dst = tab_a(b) + tab_row(p, n1, 4) + k0;
+                    float2 *dst = tab_a(b) + tab_row(p, T::wa, T::pada) + k0;
                     for (int kk = 0; kk < kend; ++kk) {
                         dst[kk] = make_float2(fq * fc, -fq * fs);
                         const float t = fc * c1 - fs * s1;
@@ -281,7 +317,7 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                         fc = t;
                     }
                 } else if (d == 1) {
-                    float2 *dst = tab_b(b) + tab_row(p, M, padb) + n;
+                    float2 *dst = tab_b(b) + tab_row(p, T::wb, T::padb) + n;
                     for (int kk = 0; kk < kend; ++kk) {
                         const int k = k0 + kk;
                         dst[k] = make_float2(fc, -fs);
@@ -355,31 +391,38 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
         dcd[(2 * nt + 1) * 64] = 0.0;
     }
 
+    // lane bases of the a and b rows of particle 8 g of a chunk, column of the lane's row
+    int abase[NTW], bbase[NTW];
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt) {
+        abase[nt] = tab_row(8 * g, T::wa, T::pada) + rnx[nt];
+        bbase[nt] = tab_row(8 * g, T::wb, T::padb) + rnyo[nt];
+    }
+
     __syncthreads();  // chunk 0's tables
-    for (int64_t c = 0; c < nchunks; ++c) {
+    // groups of 2^kDepFlipLog chunks; the running sums change sign between groups
+    for (int64_t c0 = 0; c0 < nchunks; c0 += (1 << kDepFlipLog)) {
+      const int64_t ce = c0 + (1 << kDepFlipLog) < nchunks ? c0 + (1 << kDepFlipLog) : nchunks;
+      for (int64_t c = c0; c < ce; ++c) {
         const int b = (int)(c & 1);
-        if (c > 0 && (c & ((1 << kDepFlipLog) - 1)) == 0) {
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < NTW; ++nt) {
-                    acc[mt][nt][0] = -acc[mt][nt][0];
-                    acc[mt][nt][1] = -acc[mt][nt][1];
-                }
-        }
         const float2 *ta = tab_a(b), *tb = tab_b(b);
         const _Float16 *chi = cs_hi(b), *clo = cs_lo(b);
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt) {
             half8 bre_h, bre_l, bim_h, bim_l;
             float sre = 0.f, sim = 0.f;
+            // one 8-byte read per table entry: the compiler would otherwise pair
+            // the reads of two particles into one two-address read, whose halves
+            // fall in overlapping banks (the group padding is laid out for single
+            // reads) and which runs slower
+            lds_f2 *pa = (lds_f2 *)(ta + abase[nt]);
+            lds_f2 *pbt = (lds_f2 *)(tb + bbase[nt]);
 #pragma unroll
             for (int i = 0; i < 8; i += 2) {
-                const int p0 = 8 * g + i;
-                const float2 a0 = ta[tab_row(p0, n1, 4) + rnx[nt]];
-                const float2 b0 = tb[tab_row(p0, M, padb) + rnyo[nt]];
-                const float2 a1 = ta[tab_row(p0 + 1, n1, 4) + rnx[nt]];
-                const float2 b1 = tb[tab_row(p0 + 1, M, padb) + rnyo[nt]];
+                const float2 a0 = lds_read(pa + i * T::wa);
+                const float2 b0 = lds_read(pbt + i * T::wb);
+                const float2 a1 = lds_read(pa + (i + 1) * T::wa);
+                const float2 b1 = lds_read(pbt + (i + 1) * T::wb);
                 float2_t hr, hm;
                 hr[0] = a0.x * b0.x - a0.y * b0.y;
                 hm[0] = a0.x * b0.y + a0.y * b0.x;
@@ -389,8 +432,8 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                 sim += hm[0] + hm[1];
                 const half2_t rh = __builtin_convertvector(hr, half2_t);
                 const half2_t mh = __builtin_convertvector(hm, half2_t);
-                const half2_t rl = __builtin_convertvector(hr - __builtin_convertvector(rh, float2_t), half2_t);
-                const half2_t ml = __builtin_convertvector(hm - __builtin_convertvector(mh, float2_t), half2_t);
+                const half2_t rl = split_lo2(hr, rh);
+                const half2_t ml = split_lo2(hm, mh);
                 bre_h[i] = rh[0];
                 bre_h[i + 1] = rh[1];
                 bre_l[i] = rl[0];
@@ -419,6 +462,16 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
             }
         }
         __syncthreads();
+      }
+      if (ce < nchunks) {
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+              for (int nt = 0; nt < NTW; ++nt) {
+                  acc[mt][nt][0] = -acc[mt][nt][0];
+                  acc[mt][nt][1] = -acc[mt][nt][1];
+              }
+      }
     }
 
     // after chunk c the running sums carry the sign (-1)^((c >> kDepFlipLog) & 1)
@@ -464,10 +517,24 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     }
 }
 
+template <int MT>
+static constexpr size_t deposit_mfma_lds_mt()
+{
+    return 2 * dep_buf_bytes<MT>() + (size_t)kDepCompW * dep_ntw(MT) * 2 * 64 * sizeof(double);
+}
+
 size_t deposit_mfma_lds(int n)
 {
-    const int MT = mfma_cs_tiles(n);
-    return 2 * dep_buf_bytes(n, MT) + (size_t)kDepCompW * dep_ntw(MT) * 2 * 64 * sizeof(double);
+    switch (mfma_cs_tiles(n)) {
+    case 1: return deposit_mfma_lds_mt<1>();
+    case 2: return deposit_mfma_lds_mt<2>();
+    case 3: return deposit_mfma_lds_mt<3>();
+    case 4: return deposit_mfma_lds_mt<4>();
+    case 5: return deposit_mfma_lds_mt<5>();
+    case 6: return deposit_mfma_lds_mt<6>();
+    case 7: return deposit_mfma_lds_mt<7>();
+    default: return deposit_mfma_lds_mt<8>();
+    }
 }
 
 // Particle splits: one block per (row block, split) holds a whole CU (16
@@ -566,6 +633,10 @@ k_row_info(const float *__restrict__ ftab, const float *__restrict__ psi0, int n
     int e = 0;
     if (m > 0.f) {
         frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+        // both 2^e and 2^-e stay normal FP32 numbers: a row whose largest entry
+        // is subnormal (deeply smoothed modes) is scaled by 2^126 only, instead
+        // of by an overflowing 2^-e
+        e = e < -126 ? -126 : (e > 126 ? 126 : e);
     }
     rinfo[r] = make_float4(psi0[2 * r], psi0[2 * r + 1], m > 0.f ? ldexpf(1.0f, e) : 1.0f, 0.f);
 }

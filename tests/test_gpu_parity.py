@@ -55,6 +55,9 @@ def _cases():
         ("plasma32", workloads.random_plasma(N=4099, n_max=32, a=0.01)),
         ("n40", workloads.random_particles(700, L=1.0, charge="alternating").with_(n_max=40, a=0.01)),
         ("n64", workloads.random_particles(257, L=1.3, charge="uniform").with_(n_max=64, a=0.01)),
+        # strong smoothing: S(k)^2 underflows FP32 for the outer modes, whole rows
+        # of the force table are zero or subnormal
+        ("n48_smooth", workloads.random_particles(500, L=1.0, charge="alternating").with_(n_max=48, a=0.05)),
     ]
 
 
