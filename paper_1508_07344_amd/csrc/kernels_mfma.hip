@@ -612,54 +612,112 @@ hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q
 }
 
 // ------------------------------------------------------------------ force table pack
-// Row information for the force: rinfo[r] = (Re psi(r, 0), Im psi(r, 0), scale,
-// 0) for r < R, zero for the padding rows up to a whole quad.  scale is the
-// power of two at or above the row's largest |entry| (1 for an all-zero row),
-// so that every row enters FP16 with magnitude <= 1 and small rows keep their
-// own relative precision; power-of-two scaling is exact.
-__global__ void __launch_bounds__(256)
-k_row_info(const float *__restrict__ ftab, const float *__restrict__ psi0, int n, int R, int Rq,
-           int nzp, float4 *__restrict__ rinfo)
+// The force visits rows in quads of 4 (one row per lane group).  Every n_x
+// line is padded to whole quads so that no quad mixes two lines: line 0
+// (n_x = 0, n_y = 0..n) has q0 quads, lines n_x = 1..n have qL quads each, and
+// the row arrays are padded further to a multiple of kForceQuadAlign quads
+// (whole LDS stages of the force kernel).
+// Padding rows carry zero weights.
+constexpr int kForceQuadAlign = 16;
+// quads per LDS stage of the force kernel for KS K steps of 32
+template <int KS>
+constexpr int force_tm() { return 8; }
+
+struct ForceQuads {
+    int q0, qL, Q, Qpad;
+};
+
+__host__ __device__ inline ForceQuads force_quads(int n)
 {
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    if (r >= Rq) return;
-    if (r >= R) {
-        rinfo[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+    ForceQuads f;
+    f.q0 = (n + 1 + 3) / 4;
+    f.qL = (2 * n + 1 + 3) / 4;
+    f.Q = f.q0 + n * f.qL;
+    f.Qpad = (f.Q + kForceQuadAlign - 1) / kForceQuadAlign * kForceQuadAlign;
+    return f;
+}
+
+// padded row pr = 4 t + i (quad t, lane group i) -> row of the row layout, or
+// -1 for a padding row; (nx, ny) of the row
+__host__ __device__ inline int force_row(int pr, int n, const ForceQuads &f, int &nx, int &ny)
+{
+    const int t = pr >> 2, i = pr & 3;
+    if (t >= f.Q) return -1;
+    if (t < f.q0) {
+        nx = 0;
+        ny = 4 * t + i;
+        return ny <= n ? ny : -1;
+    }
+    const int l = (t - f.q0) / f.qL, pos = 4 * ((t - f.q0) - l * f.qL) + i;
+    nx = l + 1;
+    ny = pos - n;
+    return pos < 2 * n + 1 ? (n + 1) + l * (2 * n + 1) + pos : -1;
+}
+
+// Per padded row, two records of four floats:
+//   A = (Re psi(r, 0) / s, Im psi(r, 0) / s, 0, 0): the matrix core's starting
+//       accumulator of (Re U0, Im U0, Re U1, Im U1) / s, so the n_z = 0 term
+//       costs no vector instruction;
+//   B = (n_x s, n_y s, s, 0): the weights of Im(g U0) / s in F_x and F_y, and
+//       of Im(g U1) / s in F_z.
+// s is the power of two at or above the row's largest |entry| (1 for an
+// all-zero row), so that every entry enters FP16 with magnitude <= 1 and small
+// rows keep their own relative precision; power-of-two scaling is exact.  s is
+// kept within the normal FP32 range, and no smaller than 2^-60 |psi(r, 0)| so
+// that psi / s stays far from overflow.  Records are stored interleaved,
+// rinfo[2 pr] = A, rinfo[2 pr + 1] = B, for 4 Qpad padded rows.
+__global__ void __launch_bounds__(256)
+k_force_rows(const float *__restrict__ ftab, const float *__restrict__ psi0, int n, int nzp,
+             float4 *__restrict__ rinfo)
+{
+    const ForceQuads f = force_quads(n);
+    const int pr = blockIdx.x * 256 + threadIdx.x;
+    if (pr >= 4 * f.Qpad) return;
+    int nx = 0, ny = 0;
+    const int r = force_row(pr, n, f, nx, ny);
+    if (r < 0) {
+        rinfo[2 * pr] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rinfo[2 * pr + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
         return;
     }
     float m = 0.f;
-    const float *f = ftab + (int64_t)r * nzp * 8;
-    for (int i = 0; i < n * 8; ++i) m = fmaxf(m, fabsf(f[i]));
+    const float *fr = ftab + (int64_t)r * nzp * 8;
+    for (int i = 0; i < n * 8; ++i) m = fmaxf(m, fabsf(fr[i]));
+    const float pre = psi0[2 * r], pim = psi0[2 * r + 1];
+    m = fmaxf(m, ldexpf(fmaxf(fabsf(pre), fabsf(pim)), -60));
     int e = 0;
     if (m > 0.f) {
         frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
-        // both 2^e and 2^-e stay normal FP32 numbers: a row whose largest entry
-        // is subnormal (deeply smoothed modes) is scaled by 2^126 only, instead
-        // of by an overflowing 2^-e
         e = e < -126 ? -126 : (e > 126 ? 126 : e);
     }
-    rinfo[r] = make_float4(psi0[2 * r], psi0[2 * r + 1], m > 0.f ? ldexpf(1.0f, e) : 1.0f, 0.f);
+    const float s = m > 0.f ? ldexpf(1.0f, e) : 1.0f;
+    const float inv = m > 0.f ? ldexpf(1.0f, -e) : 1.0f;
+    rinfo[2 * pr] = make_float4(pre * inv, pim * inv, 0.f, 0.f);
+    rinfo[2 * pr + 1] = make_float4((float)nx * s, (float)ny * s, s, 0.f);
 }
 
-// W fragments: wf[t][s][h][lane][8] halves, t = row quad (rows 4t..4t+3),
-// s = K step, h = hi/lo.  Lane l, element i: A row m = l % 16 -> row 4t + m/4,
-// component m % 4; K index k = 32 s + 8 (l/16) + i -> cos (k < nzk) or sin of
+// W fragments: wf[t][s][h][lane][8] halves, t = quad (< Qpad), s = K step, h = hi/lo.
+// Lane l, element i: A row m = l % 16 -> padded row 4t + m/4, component
+// e = m % 4; K index k = 32 s + 8 (l/16) + i -> cos (k < nzk) or sin of
 // n_z = (k mod nzk) + 1.
 __global__ void __launch_bounds__(256)
-k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, int n, int R, int nzp,
-             int nzk, int quads, int ks, _Float16 *__restrict__ wf)
+k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, int n, int nzp,
+             int nzk, int ks, _Float16 *__restrict__ wf)
 {
+    const ForceQuads f = force_quads(n);
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t total = (int64_t)quads * ks * 64;
+    const int64_t total = (int64_t)f.Qpad * ks * 64;
     if (gid >= total) return;
     const int lane = (int)(gid & 63);
     const int64_t ts = gid >> 6;
     const int s = (int)(ts % ks);
     const int t = (int)(ts / ks);
-    const int m = lane & 15;
-    const int r = 4 * t + (m >> 2);
-    const int e = m & 3;
-    const float inv = r < R ? 1.0f / rinfo[r].z : 1.0f;
+    const int mrow = lane & 15;
+    const int pr = 4 * t + (mrow >> 2);
+    const int e = mrow & 3;
+    int nx, ny;
+    const int r = force_row(pr, n, f, nx, ny);
+    const float inv = r >= 0 ? 1.0f / rinfo[2 * pr + 1].z : 1.0f;
     _Float16 hi[8], lo[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -667,14 +725,14 @@ k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, i
         const bool is_sin = k >= nzk;
         const int nz = (is_sin ? k - nzk : k) + 1;
         float v = 0.f;
-        if (r < R && nz <= n) {
-            const float *f = ftab + ((int64_t)r * nzp + (nz - 1)) * 8;
-            // f: sig_r sig_i del_r del_i nz*del_r nz*del_i nz*sig_r nz*sig_i
+        if (r >= 0 && nz <= n) {
+            const float *fe = ftab + ((int64_t)r * nzp + (nz - 1)) * 8;
+            // fe: sig_r sig_i del_r del_i nz*del_r nz*del_i nz*sig_r nz*sig_i
             switch (e) {
-            case 0: v = is_sin ? -f[3] : f[0]; break;  // Re U0: sig_r cos - del_i sin
-            case 1: v = is_sin ? f[2] : f[1]; break;   // Im U0: sig_i cos + del_r sin
-            case 2: v = is_sin ? -f[7] : f[4]; break;  // Re U1: nz (del_r cos - sig_i sin)
-            default: v = is_sin ? f[6] : f[5]; break;  // Im U1: nz (del_i cos + sig_r sin)
+            case 0: v = is_sin ? -fe[3] : fe[0]; break;  // Re U0: sig_r cos - del_i sin
+            case 1: v = is_sin ? fe[2] : fe[1]; break;   // Im U0: sig_i cos + del_r sin
+            case 2: v = is_sin ? -fe[7] : fe[4]; break;  // Re U1: nz (del_r cos - sig_i sin)
+            default: v = is_sin ? fe[6] : fe[5]; break;  // Im U1: nz (del_i cos + sig_r sin)
             }
         }
         split_f16(v * inv, hi[i], lo[i]);
@@ -687,44 +745,49 @@ k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, i
     }
 }
 
-size_t force_rowinfo_bytes(const Geom &g) { return (size_t)(g.R + 3) / 4 * 4 * sizeof(float4); }
+size_t force_rowinfo_bytes(const Geom &g) { return (size_t)2 * 4 * force_quads(g.n).Qpad * sizeof(float4); }
 
 hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0, const Geom &g,
                              float4 *rinfo, _Float16 *wf)
 {
-    const int quads = (g.R + 3) / 4;
-    hipLaunchKernelGGL(k_row_info, dim3((4 * quads + 255) / 256), dim3(256), 0, s, ftab, psi0, g.n,
-                       g.R, 4 * quads, g.nzp, rinfo);
+    const ForceQuads f = force_quads(g.n);
+    hipLaunchKernelGGL(k_force_rows, dim3((4 * f.Qpad + 255) / 256), dim3(256), 0, s, ftab, psi0, g.n,
+                       g.nzp, rinfo);
     const int nzk = (g.n + 15) / 16 * 16;
     const int ks = nzk / 16;
-    const int64_t total = (int64_t)quads * ks * 64;
+    const int64_t total = (int64_t)f.Qpad * ks * 64;
     hipLaunchKernelGGL(k_force_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ftab,
-                       rinfo, g.n, g.R, g.nzp, nzk, quads, ks, wf);
+                       rinfo, g.n, g.nzp, nzk, ks, wf);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ force
 // Block = 8 waves x 32 particles (NT = 2 N tiles of 16 particles per wave).
-// The W fragments and row information of kForceTM row quads at a time are
+// The W fragments and row records of kForceTM quads at a time (a stage) are
 // copied into LDS for the whole block with direct global-to-LDS loads, double
-// buffered in two separate LDS arrays: the next quads stream into one while
-// the current ones are multiplied out of the other, one barrier per kForceTM
-// quads.  (With the buffers as distinct objects the compiler can tell that
-// reads of the current one need not wait for the copies into the other.)
-// Every wave keeps its particles' CS fragments in registers.  The lane group
-// g = l/16 handles row 4t + g of each quad t, so the four groups sum disjoint
-// rows of the same particles and are combined at the end.  The matrix
-// products of quad t+1 are issued before the VALU epilogue of quad t.
+// buffered in two separate LDS arrays: the next stage streams into one while
+// the current one is multiplied out of the other, one barrier per stage.  The
+// quads are padded to whole stages (the padding contributes zero), so every
+// stage runs the same fixed loop.  (With
+// the buffers as distinct objects the compiler can tell that reads of the
+// current one need not wait for the copies into the other.)  Every wave keeps
+// its particles' CS fragments in registers.  Lane group g = l/16 handles row
+// 4t + g of each quad t, so the four groups sum disjoint rows of the same
+// particles and are combined at the end.  The matrix products of quad t+1 are
+// issued before the epilogue of quad t.
 //
-// Phase g = exp(2 pi i (nx tx + ny ty)) of the lane's row: stepping 4 rows
-// multiplies it by e4 = cis(4 ty) within a line, or by
-// ew = e4 cis(tx - (2n+1) ty) when the step wraps into the next n_x line, so
-// every lane does the same work whichever line it is on.  Every
-// kForceAnchor stages all lanes re-anchor g exactly (FP64 sincos of the
-// exactly reduced phase) and add their FP32 sums into FP64.  PHI: also sum
+// The epilogue of a (quad, 16-particle tile) is 11 vector instructions: with
+// the accumulator started at psi(r, 0) / s (record A), the matrix core returns
+// (U0, U1) / s, and
+//   Im(g U0) / s, Im(g U1) / s       4
+//   F += (n_x s, n_y s, s) (...)     3   (record B)
+//   g <- g cis(4 theta_y)            4
+// where g = exp(2 pi i (n_x t_x + n_y t_y)) is the lane's row phase in FP32.
+// Quads never cross lines, so the step is the same for every lane.  At each
+// line end the FP32 sums go into FP64 and g restarts from the next line's
+// phase, kept by an FP64 complex recurrence in t_x (exact to ~1e-15 over all
+// lines), so FP32 phase steps never run longer than one line.  PHI: also sum
 // the potential (only the diagnostics need it).
-constexpr int kForceTM = 8;
-constexpr int kForceAnchor = 2;
 constexpr int kForceWaves = 8;
 constexpr int kForceNT = 2;
 constexpr int kForceBlockParticles = kForceWaves * kForceNT * 16;
@@ -740,19 +803,20 @@ __device__ inline void stage_w(const half8 *__restrict__ src, half8 *dst, int np
             (__attribute__((address_space(3))) void *)(dst + 64 * p), 16, 0, 0);
 }
 
-// keeps a value materialised in a VGPR in its current type
-__device__ inline void keep(float &x) { asm volatile("" : "+v"(x)); }
-
 template <int KS, bool PHI>
-__global__ void __launch_bounds__(512, 2)
+__global__ void __launch_bounds__(64 * kForceWaves, 2)
 k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
              const double *__restrict__ m, double *__restrict__ vel, const _Float16 *__restrict__ wf,
-             const float4 *__restrict__ rinfo, int n, int quads, double invL, int64_t N, double kick,
+             const float4 *__restrict__ rinfo, int n, double invL, int64_t N, double kick,
              double *__restrict__ F, double *__restrict__ phi)
 {
     constexpr int NT = kForceNT;
+    constexpr int kForceTM = force_tm<KS>();
+    constexpr int kForceRecWaves = (8 * kForceTM + 63) / 64;  // waves that load a stage's row records
+    static_assert(kForceRecWaves <= kForceWaves && kForceTM % 2 == 0 && kForceQuadAlign % kForceTM == 0,
+                  "stage shape");
     constexpr int PIECES = kForceTM * KS * 2;          // 1 KB W pieces per stage
-    constexpr int STAGE = PIECES * 64 + 4 * kForceTM;  // half8 per stage buffer (W, then row info)
+    constexpr int STAGE = PIECES * 64 + 8 * kForceTM;  // half8 per stage buffer (W, records A, B)
     __shared__ half8 wbuf0[STAGE], wbuf1[STAGE];
 
     const int tid = threadIdx.x;
@@ -761,35 +825,35 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
     const int g = lane >> 4;
     const int ln = lane & 15;
     const int nzk = 16 * KS;
-    const int M = 2 * n + 1;
+    const ForceQuads fq = force_quads(n);
     const half8 *wsrc = reinterpret_cast<const half8 *>(wf);
     const half8 *isrc = reinterpret_cast<const half8 *>(rinfo);
-    const int nstage = (quads + kForceTM - 1) / kForceTM;
+    const int nstage = fq.Qpad / kForceTM;  // padding quads contribute zero
 
     auto stage = [&](int st, half8 *dst) {
         const int t0 = st * kForceTM;
-        const int cnt = quads - t0 < kForceTM ? quads - t0 : kForceTM;
-        stage_w(wsrc + (int64_t)t0 * KS * 2 * 64, dst, cnt * KS * 2, wave, lane);
-        if (wave == kForceWaves - 1 && lane < 4 * cnt)
-            __builtin_amdgcn_global_load_lds((const void *)(isrc + 4 * t0 + lane),
-                                             (__attribute__((address_space(3))) void *)(dst + PIECES * 64),
+        stage_w(wsrc + (int64_t)t0 * KS * 2 * 64, dst, PIECES, wave, lane);
+        // the interleaved records A, B of the stage's 4 kForceTM rows, one per
+        // lane (the array is padded to whole stages)
+        const int rw = wave - (kForceWaves - kForceRecWaves);
+        if (rw >= 0 && 64 * rw + lane < 8 * kForceTM)
+            __builtin_amdgcn_global_load_lds((const void *)(isrc + 8 * t0 + 64 * rw + lane),
+                                             (__attribute__((address_space(3))) void *)(dst + PIECES * 64 + 64 * rw),
                                              16, 0, 0);
     };
     // first stage in flight while the particle fragments are formed
     stage(0, wbuf0);
 
     half8 bh[NT][KS], bl[NT][KS];
-    double tx[NT], ty[NT];
-    float gc[NT], gs[NT], e4c[NT], e4s[NT], ewc[NT], ews[NT];
+    float gc[NT], gs[NT], e4c[NT], e4s[NT];
+    double lc[NT], ls[NT], stc[NT], sts[NT];  // next line's phase; step cis(t_x)
     double fx[NT], fy[NT], fz[NT], fp[NT];
-    int nx, ny;
-    row_nxny(g, n, nx, ny);  // row g < 4 < R
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int64_t j = (int64_t)blockIdx.x * kForceBlockParticles + wave * (NT * 16) + nt * 16 + ln;
         const int64_t jc = j < N ? j : N - 1;
-        tx[nt] = frac(pos[jc] * invL);
-        ty[nt] = frac(pos[N + jc] * invL);
+        const double tx = frac(pos[jc] * invL);
+        const double ty = frac(pos[N + jc] * invL);
         const double tz = frac(pos[2 * N + jc] * invL);
         double ezc, ezs;
         cis_turns(tz, ezc, ezs);
@@ -813,26 +877,21 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
             }
         }
         double a, b;
-        cis_turns(frac_mul(4, ty[nt]), a, b);
+        cis_turns(frac_mul(4, ty), a, b);
         e4c[nt] = (float)a;
         e4s[nt] = (float)b;
-        cis_turns(frac_lin(1, tx[nt], 4 - M, ty[nt]), a, b);
-        ewc[nt] = (float)a;
-        ews[nt] = (float)b;
-        keep(e4c[nt]);
-        keep(e4s[nt]);
-        keep(ewc[nt]);
-        keep(ews[nt]);
-        cis_turns(frac_lin(nx, tx[nt], ny, ty[nt]), a, b);
+        // line 0 starts at n_y = g; line 1 at (n_x, n_y) = (1, g - n)
+        cis_turns(frac_mul(g, ty), a, b);
         gc[nt] = (float)a;
         gs[nt] = (float)b;
+        cis_turns(frac_lin(1, tx, g - n, ty), lc[nt], ls[nt]);
+        cis_turns(tx, stc[nt], sts[nt]);
         fx[nt] = fy[nt] = fz[nt] = fp[nt] = 0.0;
     }
     float sx[NT], sy[NT], sz[NT], sp[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) sx[nt] = sy[nt] = sz[nt] = sp[nt] = 0.f;
-    float fnx = (float)nx, fny = (float)ny;
-    const float fn = (float)n, fM = (float)M;
+    int next_line = fq.q0;  // first quad of the next line
 
     auto products = [&](const half8 *wl, int tt, f32x4 (&acc)[NT]) {
         half8 ah[KS], al[KS];
@@ -841,58 +900,31 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
             ah[s] = wl[((tt * KS + s) * 2 + 0) * 64 + lane];
             al[s] = wl[((tt * KS + s) * 2 + 1) * 64 + lane];
         }
+        const float4 ci = reinterpret_cast<const float4 *>(wl + PIECES * 64)[2 * (4 * tt + g)];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            acc[nt] = f32x4{ci.x, ci.y, ci.z, ci.w};
 #pragma unroll
             for (int s = 0; s < KS; ++s) acc[nt] = mfma_split(ah[s], al[s], bh[nt][s], bl[nt][s], acc[nt]);
         }
     };
-    auto epilogue = [&](const float4 *ri, int tt, const f32x4 (&acc)[NT]) {
-        const float4 inf = ri[4 * tt + g];  // psi(r, 0), scale (zero past the last row)
+    auto epilogue = [&](const half8 *wl, int tt, int t, const f32x4 (&acc)[NT]) {
+        const float4 w = reinterpret_cast<const float4 *>(wl + PIECES * 64)[2 * (4 * tt + g) + 1];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            const float u0r = fmaf(acc[nt][0], inf.z, inf.x), u0i = fmaf(acc[nt][1], inf.z, inf.y);
-            const float u1r = acc[nt][2] * inf.z, u1i = acc[nt][3] * inf.z;
-            const float im0 = gc[nt] * u0i + gs[nt] * u0r;
-            const float im1 = gc[nt] * u1i + gs[nt] * u1r;
-            sx[nt] = fmaf(fnx, im0, sx[nt]);
-            sy[nt] = fmaf(fny, im0, sy[nt]);
-            sz[nt] += im1;
-            if (PHI) sp[nt] += gc[nt] * u0r - gs[nt] * u0i;
-        }
-        // next row of this lane group: r + 4, possibly into the next n_x line
-        fny += 4.f;
-        const bool wrap = fny > fn;
-        if (wrap) {
-            fny -= fM;
-            fnx += 1.f;
-        }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const float mc = wrap ? ewc[nt] : e4c[nt], ms = wrap ? ews[nt] : e4s[nt];
-            const float c = gc[nt] * mc - gs[nt] * ms;
-            gs[nt] = gs[nt] * mc + gc[nt] * ms;
+            const float im0 = gc[nt] * acc[nt][1] + gs[nt] * acc[nt][0];
+            const float im1 = gc[nt] * acc[nt][3] + gs[nt] * acc[nt][2];
+            sx[nt] = fmaf(w.x, im0, sx[nt]);
+            sy[nt] = fmaf(w.y, im0, sy[nt]);
+            sz[nt] = fmaf(w.z, im1, sz[nt]);
+            if (PHI) sp[nt] = fmaf(w.z, gc[nt] * acc[nt][0] - gs[nt] * acc[nt][1], sp[nt]);
+            const float c = gc[nt] * e4c[nt] - gs[nt] * e4s[nt];
+            gs[nt] = gs[nt] * e4c[nt] + gc[nt] * e4s[nt];
             gc[nt] = c;
         }
-    };
-    auto run_stage = [&](int st, const half8 *wl, half8 *next) {
-        const int t0 = st * kForceTM;
-        const int tcnt = quads - t0 < kForceTM ? quads - t0 : kForceTM;
-        const float4 *ri = reinterpret_cast<const float4 *>(wl + PIECES * 64);
-        if (st + 1 < nstage) stage(st + 1, next);
-        f32x4 accA[NT], accB[NT];
-        products(wl, 0, accA);
-        for (int tt = 0; tt < tcnt; tt += 2) {
-            if (tt + 1 < tcnt) products(wl, tt + 1, accB);
-            epilogue(ri, tt, accA);
-            if (tt + 1 >= tcnt) break;
-            if (tt + 2 < tcnt) products(wl, tt + 2, accA);
-            epilogue(ri, tt + 1, accB);
-        }
-        if ((st + 1) % kForceAnchor == 0 || st + 1 == nstage) {
-            nx = (int)fnx;
-            ny = (int)fny;
+        if (t + 1 == next_line) {
+            // end of a line: FP32 sums into FP64, phase of the next line's first row
+            next_line += fq.qL;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 fx[nt] += (double)sx[nt];
@@ -900,11 +932,25 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
                 fz[nt] += (double)sz[nt];
                 if (PHI) fp[nt] += (double)sp[nt];
                 sx[nt] = sy[nt] = sz[nt] = sp[nt] = 0.f;
-                double a, b;
-                cis_turns(frac_lin(nx, tx[nt], ny, ty[nt]), a, b);
-                gc[nt] = (float)a;
-                gs[nt] = (float)b;
+                gc[nt] = (float)lc[nt];
+                gs[nt] = (float)ls[nt];
+                const double c = lc[nt] * stc[nt] - ls[nt] * sts[nt];
+                ls[nt] = lc[nt] * sts[nt] + ls[nt] * stc[nt];
+                lc[nt] = c;
             }
+        }
+    };
+    auto run_stage = [&](int st, const half8 *wl, half8 *next) {
+        const int t0 = st * kForceTM;
+        if (st + 1 < nstage) stage(st + 1, next);
+        f32x4 accA[NT], accB[NT];
+        products(wl, 0, accA);
+#pragma unroll 1
+        for (int tt = 0; tt < kForceTM; tt += 2) {
+            products(wl, tt + 1, accB);
+            epilogue(wl, tt, t0 + tt, accA);
+            if (tt + 2 < kForceTM) products(wl, tt + 2, accA);
+            epilogue(wl, tt + 1, t0 + tt + 1, accB);
         }
         // the next stage's copies have landed, and every wave is done with this one
         __builtin_amdgcn_s_waitcnt(0);
@@ -949,39 +995,36 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
 template <int KS>
 static void launch_force_ks(hipStream_t s, dim3 grid, dim3 block, const double *pos, const double *q,
                             const double *m, double *vel, const _Float16 *wf, const float4 *rinfo,
-                            int n, int quads, double invL, int64_t N, double kick, double *F,
-                            double *phi)
+                            int n, double invL, int64_t N, double kick, double *F, double *phi)
 {
     if (phi)
         hipLaunchKernelGGL((k_force_mfma<KS, true>), grid, block, 0, s, pos, q, m, vel, wf, rinfo, n,
-                           quads, invL, N, kick, F, phi);
+                           invL, N, kick, F, phi);
     else
         hipLaunchKernelGGL((k_force_mfma<KS, false>), grid, block, 0, s, pos, q, m, vel, wf, rinfo, n,
-                           quads, invL, N, kick, F, phi);
+                           invL, N, kick, F, phi);
 }
 
 hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, const double *m,
                              double *vel, const _Float16 *wf, const float4 *rinfo, const Geom &g,
                              double L, int64_t N, double kick, double *F, double *phi)
 {
-    const int quads = (g.R + 3) / 4;
     const int ks = (g.n + 15) / 16;
     const int64_t blocks = (N + kForceBlockParticles - 1) / kForceBlockParticles;
     const dim3 grid((unsigned)blocks), block(64 * kForceWaves);
     switch (ks) {
-    case 1: launch_force_ks<1>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, quads, 1.0 / L, N, kick, F, phi); break;
-    case 2: launch_force_ks<2>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, quads, 1.0 / L, N, kick, F, phi); break;
-    case 3: launch_force_ks<3>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, quads, 1.0 / L, N, kick, F, phi); break;
-    default: launch_force_ks<4>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, quads, 1.0 / L, N, kick, F, phi); break;
+    case 1: launch_force_ks<1>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, 1.0 / L, N, kick, F, phi); break;
+    case 2: launch_force_ks<2>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, 1.0 / L, N, kick, F, phi); break;
+    case 3: launch_force_ks<3>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, 1.0 / L, N, kick, F, phi); break;
+    default: launch_force_ks<4>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, 1.0 / L, N, kick, F, phi); break;
     }
     return hipGetLastError();
 }
 
 size_t force_pack_bytes(const Geom &g)
 {
-    const int quads = (g.R + 3) / 4;
     const int ks = (g.n + 15) / 16;
-    return (size_t)quads * ks * 2 * 64 * 8 * sizeof(_Float16);
+    return (size_t)force_quads(g.n).Qpad * ks * 2 * 64 * 8 * sizeof(_Float16);
 }
 
 }  // namespace sce
