@@ -154,10 +154,10 @@ k_deposit_prep(const double *__restrict__ pos, const double *__restrict__ q, int
 // banks.  b table (16 MT + 1 entries, k = -n..n used around column n): the
 // group padding of 8 float2 makes the groups' rows start 128 bytes apart
 // modulo the 256-byte bank cycle, so that lane groups 0/1 and 2/3, which read
-// 16 consecutive entries each in the same pass, use disjoint banks.  CS rows
-// hold 32 particles plus 8 halves of padding (80-byte stride), so that the 16
-// rows read by a lane group's 16-byte fragment loads fall in distinct banks.
-// A table entry read as a volatile LDS double, which the compiler keeps as a
+// 16 consecutive entries each in the same pass, use disjoint banks.  The CS
+// operand is stored in the matrix core's fragment order (cs_idx), so that a
+// lane's 16-byte fragment read is at 16 lane + const: 16-byte LDS reads run at
+// full rate only when the lanes' addresses are consecutive.  A table entry read as a volatile LDS double, which the compiler keeps as a
 // read of its own.
 typedef const volatile double __attribute__((address_space(3))) lds_f2;
 __device__ inline float2 lds_read(lds_f2 *p)
@@ -174,7 +174,12 @@ struct DepTab {
     static constexpr int padb = 8;  // wb = 1 mod 4
 };
 __device__ inline int tab_row(int p, int w, int pad) { return p * w + (p >> 3) * pad; }
-constexpr int kCSP = kDepChunk + 8;
+// CS element (row, particle p of the chunk) in fragment order: tile mt =
+// row / 16 holds 64 lanes x 8 halves, lane = row % 16 + 16 (p / 8), half p % 8.
+__device__ inline int cs_idx(int row, int p)
+{
+    return (row >> 4) * 512 + (p >> 3) * 128 + (row & 15) * 8 + (p & 7);
+}
 
 // Running sums change sign every 2^kDepFlipLog chunks.
 constexpr int kDepFlipLog = 3;
@@ -190,7 +195,7 @@ template <int MT>
 __host__ __device__ constexpr size_t dep_buf_bytes()
 {
     using T = DepTab<MT>;
-    return (size_t)MT * 16 * kCSP * 2 * sizeof(_Float16) +
+    return (size_t)MT * 16 * kDepChunk * 2 * sizeof(_Float16) +
            (size_t)(kDepChunk * T::wa + 4 * T::pada + kDepChunk * T::wb + 4 * T::padb) * sizeof(float2);
 }
 
@@ -238,9 +243,9 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     constexpr size_t bufb = dep_buf_bytes<MT>();
     using T = DepTab<MT>;
     auto cs_hi = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb); };
-    auto cs_lo = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb) + CSR * kCSP; };
+    auto cs_lo = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb) + CSR * kDepChunk; };
     auto tab_a = [&](int b) {
-        return reinterpret_cast<float2 *>(smem + b * bufb + (size_t)CSR * kCSP * 2 * sizeof(_Float16));
+        return reinterpret_cast<float2 *>(smem + b * bufb + (size_t)CSR * kDepChunk * 2 * sizeof(_Float16));
     };
     auto tab_b = [&](int b) { return tab_a(b) + kDepChunk * T::wa + 4 * T::pada; };
 
@@ -252,10 +257,11 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     const int64_t nchunks = (j1 - j0 + kDepChunk - 1) / kDepChunk;
     const int nb = (n1 + 7) / 8;
 
-    for (int idx = tid; idx < (CSR - 2 * n) * kCSP; idx += kDepThreads)
+    for (int idx = tid; idx < (CSR - 2 * n) * kDepChunk; idx += kDepThreads)
         for (int b = 0; b < 2; ++b) {
-            cs_hi(b)[2 * n * kCSP + idx] = (_Float16)0.0f;
-            cs_lo(b)[2 * n * kCSP + idx] = (_Float16)0.0f;
+            const int e = cs_idx(2 * n + idx / kDepChunk, idx % kDepChunk);
+            cs_hi(b)[e] = (_Float16)0.0f;
+            cs_lo(b)[e] = (_Float16)0.0f;
         }
 
     if (wave >= kDepCompW) {
@@ -263,28 +269,36 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
         // raised issue priority: the next chunk's tables are the critical path,
         // the matrix-core waves fill the remaining issue slots
         __builtin_amdgcn_s_setprio(2);
-        // tasks (axis d, block of 8 powers blk, particle p), particle fastest;
-        // builder thread bt owns tasks bt + s 64 kDepBuildW, s < kDepSlots.
-        // The record fields of the next chunk's tasks are loaded one chunk ahead.
-        constexpr int kDepSlots = 4;  // enough for n_max <= 64
-        const int bt = tid - 64 * kDepCompW;
-        const int ntask = 3 * nb * kDepChunk;
+        // tasks (axis d, block of 8 powers blk, particle p), particle fastest.
+        // A wave takes 64 tasks at a time, a pair of blocks of one axis (the
+        // block count is padded to even per axis), so its two half-waves never
+        // take different branches: wave slot ws = 4 sl + (builder wave) is
+        // axis ws / npair, block pair ws % npair.  The record fields of the
+        // next chunk's tasks are loaded one chunk ahead.
+        constexpr int kDepSlots = 6;  // enough for n_max <= 64
+        const int bw = wave - kDepCompW;
+        const int npair = (nb + 1) / 2;
         const int rf = dep_rec_floats(n);
         float rc[kDepSlots], rs[kDepSlots], sc[kDepSlots], ss[kDepSlots], rq[kDepSlots];
+        auto task_of = [&](int sl, int &d, int &blk, int &p) {
+            const int ws = sl * kDepBuildW + bw;
+            d = ws / npair;
+            blk = 2 * (ws - d * npair) + (lane >> 5);
+            p = lane & (kDepChunk - 1);
+            return d < 3 && blk < nb;
+        };
         auto load_chunk = [&](int64_t c) {
 #pragma unroll
             for (int sl = 0; sl < kDepSlots; ++sl) {
-                const int task = bt + sl * 64 * kDepBuildW;
-                const int p = task & (kDepChunk - 1);
-                const int db = task / kDepChunk;
-                const int d = db / nb, blk = db - d * nb;
+                int d, blk, p;
+                const bool ok = task_of(sl, d, blk, p);
                 const int64_t j = j0 + c * kDepChunk + p;
                 rc[sl] = 1.f;
                 rs[sl] = 0.f;
                 sc[sl] = 1.f;
                 ss[sl] = 0.f;
                 rq[sl] = 0.f;
-                if (task < ntask && c < nchunks && j < j1) {
+                if (ok && c < nchunks && j < j1) {
                     const float *r0 = rec + j * rf;
                     rc[sl] = r0[2 * (d * nb + blk)];
                     rs[sl] = r0[2 * (d * nb + blk) + 1];
@@ -294,29 +308,32 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                 }
             }
         };
+        // Powers by complex multiplication from the block's anchor; the anchor
+        // carries the factor each table needs (q and the conjugation for a, the
+        // running-sum sign and the 7/8 operand scale for CS), so the recurrence
+        // propagates it at no cost.
         auto build_chunk = [&](int64_t c) {
             const int b = (int)(c & 1);
             const float csg = ((c >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
 #pragma unroll
             for (int sl = 0; sl < kDepSlots; ++sl) {
-                const int task = bt + sl * 64 * kDepBuildW;
-                if (task >= ntask) continue;
-                const int p = task & (kDepChunk - 1);
-                const int db = task / kDepChunk;
-                const int d = db / nb, blk = db - d * nb;
-                float fc = rc[sl], fs = rs[sl];
-                const float c1 = sc[sl], s1 = ss[sl], fq = rq[sl];
+                int d, blk, p;
+                if (!task_of(sl, d, blk, p)) continue;
+                const float c1 = sc[sl], s1 = ss[sl];
                 const int k0 = 8 * blk;
                 const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
                 if (d == 0) {
+                    // u_k = q cis(-k tx): anchor q conj(cis), step conj(cis(tx))
+                    float uc = rq[sl] * rc[sl], us = -rq[sl] * rs[sl];
                     float2 *dst = tab_a(b) + tab_row(p, T::wa, T::pada) + k0;
                     for (int kk = 0; kk < kend; ++kk) {
-                        dst[kk] = make_float2(fq * fc, -fq * fs);
-                        const float t = fc * c1 - fs * s1;
-                        fs = fc * s1 + fs * c1;
-                        fc = t;
+                        dst[kk] = make_float2(uc, us);
+                        const float t = uc * c1 + us * s1;
+                        us = us * c1 - uc * s1;
+                        uc = t;
                     }
                 } else if (d == 1) {
+                    float fc = rc[sl], fs = rs[sl];
                     float2 *dst = tab_b(b) + tab_row(p, T::wb, T::padb) + n;
                     for (int kk = 0; kk < kend; ++kk) {
                         const int k = k0 + kk;
@@ -327,21 +344,24 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                         fc = t;
                     }
                 } else {
+                    float2_t v;
+                    v[0] = csg * rc[sl];
+                    v[1] = csg * rs[sl];
                     _Float16 *hi = cs_hi(b), *lo = cs_lo(b);
                     for (int kk = 0; kk < kend; ++kk) {
                         const int k = k0 + kk;
                         if (k > 0) {
-                            _Float16 h, l;
-                            split_f16(csg * fc, h, l);
-                            hi[(k - 1) * kCSP + p] = h;
-                            lo[(k - 1) * kCSP + p] = l;
-                            split_f16(csg * fs, h, l);
-                            hi[(n + k - 1) * kCSP + p] = h;
-                            lo[(n + k - 1) * kCSP + p] = l;
+                            // (cos, sin) split two at a time
+                            const half2_t h = __builtin_convertvector(v, half2_t);
+                            const half2_t l = split_lo2(v, h);
+                            hi[cs_idx(k - 1, p)] = h[0];
+                            lo[cs_idx(k - 1, p)] = l[0];
+                            hi[cs_idx(n + k - 1, p)] = h[1];
+                            lo[cs_idx(n + k - 1, p)] = l[1];
                         }
-                        const float t = fc * c1 - fs * s1;
-                        fs = fc * s1 + fs * c1;
-                        fc = t;
+                        const float t = v[0] * c1 - v[1] * s1;
+                        v[1] = v[0] * s1 + v[1] * c1;
+                        v[0] = t;
                     }
                 }
             }
@@ -447,8 +467,8 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
             dc[nt][1] += sim;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                const half8 ah = *reinterpret_cast<const half8 *>(&chi[(mt * 16 + ln) * kCSP + 8 * g]);
-                const half8 al = *reinterpret_cast<const half8 *>(&clo[(mt * 16 + ln) * kCSP + 8 * g]);
+                const half8 ah = *reinterpret_cast<const half8 *>(&chi[(mt * 64 + lane) * 8]);
+                const half8 al = *reinterpret_cast<const half8 *>(&clo[(mt * 64 + lane) * 8]);
                 acc[mt][nt][0] = mfma_split(ah, al, bre_h, bre_l, acc[mt][nt][0]);
                 acc[mt][nt][1] = mfma_split(ah, al, bim_h, bim_l, acc[mt][nt][1]);
             }
