@@ -20,6 +20,13 @@ update sequences:
 Positions are wrapped into [0, L) after every drift (periodic box, Section 8):
 wrap(x) = x - L floor(x / L), and a result equal to L becomes 0.
 
+Two dimensions: the paper's own test problems (Sections 6 and 7) are
+two-dimensional, with line charges in the periodic square [0, L)^2 of area
+A = L^2.  Every function below takes 2-component arrays as well: positions and
+velocities [2, N], modes [n, 2] (``half_modes(n_max, dim=2)``), and the solve
+and energies divide by A instead of V.  The 2-D sums are their own plain loops
+in ``sce_oracle.c``.
+
 Energies (Section 3's discrete Lagrangian, delta field shape):
 kinetic K = 1/2 sum m |v|^2, field W (see ``field_energy``), total E = K + W,
 interaction sum_j q_j Phi_j (= 2 W), and the constant self-energy of the
@@ -84,6 +91,22 @@ def _load():
             lib.sce_oracle_potential.restype = None
             lib.sce_oracle_field_energy.argtypes = [i64, P, P, f64, f64]
             lib.sce_oracle_field_energy.restype = f64
+            lib.sce_oracle_shape_2d.argtypes = [i32, f64, f64, f64]
+            lib.sce_oracle_shape_2d.restype = f64
+            lib.sce_oracle_half_modes_2d.argtypes = [i32, P]
+            lib.sce_oracle_half_modes_2d.restype = i64
+            lib.sce_oracle_square_modes.argtypes = [i32, P]
+            lib.sce_oracle_square_modes.restype = i64
+            lib.sce_oracle_deposit_2d.argtypes = [i64, P, P, P, f64, i64, P, i32, f64, P]
+            lib.sce_oracle_deposit_2d.restype = None
+            lib.sce_oracle_psi_2d.argtypes = [i64, P, P, f64, f64, i32, f64, P]
+            lib.sce_oracle_psi_2d.restype = None
+            lib.sce_oracle_force_2d.argtypes = [i64, P, P, P, f64, i64, P, P, P]
+            lib.sce_oracle_force_2d.restype = None
+            lib.sce_oracle_potential_2d.argtypes = [i64, P, P, f64, i64, P, P, P]
+            lib.sce_oracle_potential_2d.restype = None
+            lib.sce_oracle_field_energy_2d.argtypes = [i64, P, P, f64, f64]
+            lib.sce_oracle_field_energy_2d.restype = f64
             lib.sce_oracle_threads.argtypes = []
             lib.sce_oracle_threads.restype = i32
             _lib = lib
@@ -103,33 +126,40 @@ def threads() -> int:
     return int(_load().sce_oracle_threads())
 
 
-def half_modes(n_max: int) -> np.ndarray:
-    """Half-space modes H in canonical order, int32 array [|H|, 3]."""
+def half_modes(n_max: int, dim: int = 3) -> np.ndarray:
+    """Half-space modes in canonical order, int32 array [|H|, dim] (dim 3: H;
+    dim 2: the half plane H2)."""
     lib = _load()
-    n = lib.sce_oracle_half_modes(int(n_max), None)
-    out = np.zeros((n, 3), dtype=np.int32)
-    lib.sce_oracle_half_modes(int(n_max), _p(out))
+    fn = lib.sce_oracle_half_modes if dim == 3 else lib.sce_oracle_half_modes_2d
+    n = fn(int(n_max), None)
+    out = np.zeros((n, dim), dtype=np.int32)
+    fn(int(n_max), _p(out))
     return out
 
 
-def cube_modes(n_max: int) -> np.ndarray:
-    """Every mode of the cube max|n_i| <= n_max except n = 0, int32 [M^3 - 1, 3]."""
+def cube_modes(n_max: int, dim: int = 3) -> np.ndarray:
+    """Every mode with max|n_i| <= n_max except n = 0, int32 [M^dim - 1, dim]."""
     lib = _load()
-    n = lib.sce_oracle_cube_modes(int(n_max), None)
-    out = np.zeros((n, 3), dtype=np.int32)
-    lib.sce_oracle_cube_modes(int(n_max), _p(out))
+    fn = lib.sce_oracle_cube_modes if dim == 3 else lib.sce_oracle_square_modes
+    n = fn(int(n_max), None)
+    out = np.zeros((n, dim), dtype=np.int32)
+    fn(int(n_max), _p(out))
     return out
 
 
 def shape(kind: str, a: float, k: np.ndarray) -> np.ndarray:
-    """S(k) for an array of wave vectors k [..., 3]."""
+    """S(k) for an array of wave vectors k [..., 3] or [..., 2]."""
     lib = _load()
-    k = np.asarray(k, dtype=np.float64).reshape(-1, 3)
+    k = np.asarray(k, dtype=np.float64)
+    if k.shape[-1] == 2:
+        k = k.reshape(-1, 2)
+        return np.array([lib.sce_oracle_shape_2d(SHAPES[kind], a, *kk) for kk in k])
+    k = k.reshape(-1, 3)
     return np.array([lib.sce_oracle_shape(SHAPES[kind], a, *kk) for kk in k])
 
 
 def wave_vectors(modes: np.ndarray, L: float) -> np.ndarray:
-    """k = 2 pi n / L, float64 [n_modes, 3]."""
+    """k = 2 pi n / L, float64 [n_modes, dim]."""
     return (2.0 * np.pi / L) * modes.astype(np.float64)
 
 
@@ -141,13 +171,18 @@ def wrap(x: np.ndarray, L: float) -> np.ndarray:
 
 def deposit(pos, q, L: float, modes: np.ndarray, kind: str = "gaussian", a: float = 0.0) -> np.ndarray:
     """rho_n = S(k_n) sum_j q_j exp(-i k_n . x_j) for each row of ``modes``.
-    ``pos`` is [3, N].  Returns complex128 [n_modes]."""
+    ``pos`` is [3, N] (or [2, N] with 2-component modes).  Returns complex128 [n_modes]."""
     lib = _load()
     pos = _f64(pos)
-    x, y, z = (np.ascontiguousarray(pos[d]) for d in range(3))
     q = _f64(q)
     modes = np.ascontiguousarray(modes, dtype=np.int32)
     rho = np.zeros(2 * len(modes))
+    if modes.shape[1] == 2:
+        x, y = (np.ascontiguousarray(pos[d]) for d in range(2))
+        lib.sce_oracle_deposit_2d(len(q), _p(x), _p(y), _p(q), float(L), len(modes), _p(modes),
+                                  SHAPES[kind], float(a), _p(rho))
+        return rho[0::2] + 1j * rho[1::2]
+    x, y, z = (np.ascontiguousarray(pos[d]) for d in range(3))
     lib.sce_oracle_deposit(len(q), _p(x), _p(y), _p(z), _p(q), float(L), len(modes), _p(modes),
                            SHAPES[kind], float(a), _p(rho))
     return rho[0::2] + 1j * rho[1::2]
@@ -155,26 +190,32 @@ def deposit(pos, q, L: float, modes: np.ndarray, kind: str = "gaussian", a: floa
 
 def psi(rho: np.ndarray, L: float, modes: np.ndarray, eps0: float = 1.0,
         kind: str = "gaussian", a: float = 0.0) -> np.ndarray:
-    """psi_n = S(k_n) rho_n / (eps0 |k_n|^2 V)."""
+    """psi_n = S(k_n) rho_n / (eps0 |k_n|^2 V) (V = L^3; A = L^2 in two dimensions)."""
     lib = _load()
     modes = np.ascontiguousarray(modes, dtype=np.int32)
     r = np.empty(2 * len(modes))
     r[0::2], r[1::2] = rho.real, rho.imag
     out = np.zeros_like(r)
-    lib.sce_oracle_psi(len(modes), _p(modes), _p(r), float(L), float(eps0), SHAPES[kind],
-                       float(a), _p(out))
+    fn = lib.sce_oracle_psi_2d if modes.shape[1] == 2 else lib.sce_oracle_psi
+    fn(len(modes), _p(modes), _p(r), float(L), float(eps0), SHAPES[kind], float(a), _p(out))
     return out[0::2] + 1j * out[1::2]
 
 
 def force_from_psi(pos, q, L: float, modes: np.ndarray, psi_c: np.ndarray) -> np.ndarray:
-    """F_j = 2 q_j sum_{n in H} k_n Im(psi_n exp(i k_n . x_j)), returns [3, N]."""
+    """F_j = 2 q_j sum_{n in H} k_n Im(psi_n exp(i k_n . x_j)), returns [dim, N]."""
     lib = _load()
     pos = _f64(pos)
-    x, y, z = (np.ascontiguousarray(pos[d]) for d in range(3))
     q = _f64(q)
     modes = np.ascontiguousarray(modes, dtype=np.int32)
     ps = np.empty(2 * len(modes))
     ps[0::2], ps[1::2] = psi_c.real, psi_c.imag
+    if modes.shape[1] == 2:
+        x, y = (np.ascontiguousarray(pos[d]) for d in range(2))
+        F = np.zeros(2 * len(q))
+        lib.sce_oracle_force_2d(len(q), _p(x), _p(y), _p(q), float(L), len(modes), _p(modes),
+                                _p(ps), _p(F))
+        return F.reshape(2, len(q))
+    x, y, z = (np.ascontiguousarray(pos[d]) for d in range(3))
     F = np.zeros(3 * len(q))
     lib.sce_oracle_force(len(q), _p(x), _p(y), _p(z), _p(q), float(L), len(modes), _p(modes),
                          _p(ps), _p(F))
@@ -185,46 +226,54 @@ def potential_from_psi(pos, L: float, modes: np.ndarray, psi_c: np.ndarray) -> n
     """Phi_j = 2 sum_{n in H} Re(psi_n exp(i k_n . x_j))."""
     lib = _load()
     pos = _f64(pos)
-    x, y, z = (np.ascontiguousarray(pos[d]) for d in range(3))
     modes = np.ascontiguousarray(modes, dtype=np.int32)
     ps = np.empty(2 * len(modes))
     ps[0::2], ps[1::2] = psi_c.real, psi_c.imag
     out = np.zeros(pos.shape[1])
+    if modes.shape[1] == 2:
+        x, y = (np.ascontiguousarray(pos[d]) for d in range(2))
+        lib.sce_oracle_potential_2d(pos.shape[1], _p(x), _p(y), float(L), len(modes), _p(modes),
+                                    _p(ps), _p(out))
+        return out
+    x, y, z = (np.ascontiguousarray(pos[d]) for d in range(3))
     lib.sce_oracle_potential(pos.shape[1], _p(x), _p(y), _p(z), float(L), len(modes), _p(modes),
                              _p(ps), _p(out))
     return out
 
 
 def field_energy(rho: np.ndarray, L: float, modes: np.ndarray, eps0: float = 1.0) -> float:
-    """W = (1/(eps0 V)) sum_{n in H} |rho_n|^2 / |k_n|^2 (half-space sum)."""
+    """W = (1/(eps0 V)) sum_{n in H} |rho_n|^2 / |k_n|^2 (half-space sum; A in 2-D)."""
     lib = _load()
     modes = np.ascontiguousarray(modes, dtype=np.int32)
     r = np.empty(2 * len(modes))
     r[0::2], r[1::2] = rho.real, rho.imag
-    return float(lib.sce_oracle_field_energy(len(modes), _p(modes), _p(r), float(L), float(eps0)))
+    fn = lib.sce_oracle_field_energy_2d if modes.shape[1] == 2 else lib.sce_oracle_field_energy
+    return float(fn(len(modes), _p(modes), _p(r), float(L), float(eps0)))
 
 
 def self_energy(q, L: float, modes: np.ndarray, eps0: float = 1.0, kind: str = "gaussian",
                 a: float = 0.0) -> float:
-    """Constant self-energy of the retained modes: (sum q^2/(eps0 V)) sum_H S^2/|k|^2."""
+    """Constant self-energy of the retained modes: (sum q^2/(eps0 V)) sum_H S^2/|k|^2
+    (V = L^dim)."""
     k = wave_vectors(modes, L)
     s = shape(kind, a, k)
-    return float(np.sum(np.asarray(q) ** 2) / (eps0 * L ** 3) * np.sum(s * s / np.sum(k * k, axis=1)))
+    vol = L ** modes.shape[1]
+    return float(np.sum(np.asarray(q) ** 2) / (eps0 * vol) * np.sum(s * s / np.sum(k * k, axis=1)))
 
 
 @dataclasses.dataclass
 class Fields:
     rho: np.ndarray      # complex [|H|]
     psi: np.ndarray      # complex [|H|]
-    F: np.ndarray        # [3, N]
+    F: np.ndarray        # [dim, N]
     W: float
 
 
 def fields(pos, q, L: float, n_max: int, kind: str = "gaussian", a: float = 0.0,
            eps0: float = 1.0, modes: np.ndarray | None = None) -> Fields:
-    """Deposit, solve and force at positions ``pos`` (one pass of the hot path)."""
+    """Deposit, solve and force at positions ``pos`` [dim, N] (one pass of the hot path)."""
     if modes is None:
-        modes = half_modes(n_max)
+        modes = half_modes(n_max, dim=np.asarray(pos).shape[0])
     rho = deposit(pos, q, L, modes, kind, a)
     ps = psi(rho, L, modes, eps0, kind, a)
     F = force_from_psi(pos, q, L, modes, ps)
@@ -234,8 +283,8 @@ def fields(pos, q, L: float, n_max: int, kind: str = "gaussian", a: float = 0.0,
 @dataclasses.dataclass
 class State:
     """Particle state advanced by the oracle's time steps."""
-    pos: np.ndarray   # [3, N]
-    vel: np.ndarray   # [3, N]
+    pos: np.ndarray   # [dim, N]
+    vel: np.ndarray   # [dim, N]
     q: np.ndarray
     m: np.ndarray
     L: float
@@ -256,7 +305,7 @@ class State:
 
     def _modes(self):
         if self.modes is None:
-            self.modes = half_modes(self.n_max)
+            self.modes = half_modes(self.n_max, dim=self.pos.shape[0])
         return self.modes
 
     def refresh(self):

@@ -201,6 +201,135 @@ double sce_oracle_field_energy(int64_t n_modes, const int32_t *modes, const doub
     return csum_get(&s) / (eps0 * V);
 }
 
+/* ---------------------------------------------------------------- two dimensions
+ * The paper's own test problems are two-dimensional (Section 6, the two-body
+ * problem; Section 7, the thermal plasma): particles are line charges in the
+ * periodic square [0, L)^2 of area A = L^2.  Same definitions with two
+ * components:
+ *   modes      n in Z^2, max_i |n_i| <= n_max, n != 0, k_n = 2 pi n / L.
+ *   half plane H2 = { n_x > 0 } u { n_x = 0, n_y > 0 }; canonical order
+ *              n_x = 0..n_max, then n_y = -n_max..n_max, keeping those in H2.
+ *   shape      S(k) of the two-component wave vector (Gaussian exp(-|k|^2 a^2/2),
+ *              point 1, tent sinc^2(k_x a/2) sinc^2(k_y a/2)).
+ *   deposit    rho_n = S(k_n) sum_j q_j exp(-i k_n . x_j)
+ *   solve      psi_n = S(k_n) rho_n / (eps0 |k_n|^2 A)
+ *   force      F_j = 2 q_j sum_{n in H2} k_n Im(psi_n exp(i k_n . x_j))   ([2][N])
+ *   energy     W = (1 / (eps0 A)) sum_{n in H2} |rho_n|^2 / |k_n|^2.
+ * Mode arrays hold 2 ints per mode. */
+static int in_half_plane(int nx, int ny) { return nx > 0 || (nx == 0 && ny > 0); }
+
+int64_t sce_oracle_half_modes_2d(int32_t n_max, int32_t *out)
+{
+    int64_t c = 0;
+    for (int nx = 0; nx <= n_max; ++nx)
+        for (int ny = -n_max; ny <= n_max; ++ny) {
+            if (!in_half_plane(nx, ny)) continue;
+            if (out) { out[2 * c] = nx; out[2 * c + 1] = ny; }
+            ++c;
+        }
+    return c;
+}
+
+/* All modes of the square except n = 0, lexicographic from (-n_max, -n_max). */
+int64_t sce_oracle_square_modes(int32_t n_max, int32_t *out)
+{
+    int64_t c = 0;
+    for (int nx = -n_max; nx <= n_max; ++nx)
+        for (int ny = -n_max; ny <= n_max; ++ny) {
+            if (nx == 0 && ny == 0) continue;
+            if (out) { out[2 * c] = nx; out[2 * c + 1] = ny; }
+            ++c;
+        }
+    return c;
+}
+
+/* S(k) of a two-component wave vector: the particle-shape transforms above
+ * with no third component (the tent's third factor sinc^2(0) = 1). */
+double sce_oracle_shape_2d(int32_t kind, double a, double kx, double ky)
+{
+    return sce_oracle_shape(kind, a, kx, ky, 0.0);
+}
+
+void sce_oracle_deposit_2d(int64_t N, const double *x, const double *y, const double *q, double L,
+                           int64_t n_modes, const int32_t *modes, int32_t kind, double a,
+                           double *rho)
+{
+    const double f = TWO_PI / L;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n_modes; ++i) {
+        const int nx = modes[2 * i], ny = modes[2 * i + 1];
+        csum re = {0.0, 0.0}, im = {0.0, 0.0};
+        for (int64_t j = 0; j < N; ++j) {
+            const double th = f * ((double)nx * x[j] + (double)ny * y[j]);
+            csum_add(&re, q[j] * cos(th));
+            csum_add(&im, -q[j] * sin(th));
+        }
+        const double s = sce_oracle_shape_2d(kind, a, f * nx, f * ny);
+        rho[2 * i] = s * csum_get(&re);
+        rho[2 * i + 1] = s * csum_get(&im);
+    }
+}
+
+void sce_oracle_psi_2d(int64_t n_modes, const int32_t *modes, const double *rho, double L,
+                       double eps0, int32_t kind, double a, double *psi)
+{
+    const double f = TWO_PI / L, A = L * L;
+    for (int64_t i = 0; i < n_modes; ++i) {
+        const double kx = f * modes[2 * i], ky = f * modes[2 * i + 1];
+        const double k2 = kx * kx + ky * ky;
+        const double w = sce_oracle_shape_2d(kind, a, kx, ky) / (eps0 * k2 * A);
+        psi[2 * i] = w * rho[2 * i];
+        psi[2 * i + 1] = w * rho[2 * i + 1];
+    }
+}
+
+void sce_oracle_force_2d(int64_t N, const double *x, const double *y, const double *q, double L,
+                         int64_t n_modes, const int32_t *modes, const double *psi, double *F)
+{
+    const double f = TWO_PI / L;
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < N; ++j) {
+        csum fx = {0.0, 0.0}, fy = {0.0, 0.0};
+        for (int64_t i = 0; i < n_modes; ++i) {
+            const int nx = modes[2 * i], ny = modes[2 * i + 1];
+            const double th = f * ((double)nx * x[j] + (double)ny * y[j]);
+            const double im = psi[2 * i] * sin(th) + psi[2 * i + 1] * cos(th);
+            csum_add(&fx, f * nx * im);
+            csum_add(&fy, f * ny * im);
+        }
+        F[j] = 2.0 * q[j] * csum_get(&fx);
+        F[N + j] = 2.0 * q[j] * csum_get(&fy);
+    }
+}
+
+void sce_oracle_potential_2d(int64_t N, const double *x, const double *y, double L, int64_t n_modes,
+                             const int32_t *modes, const double *psi, double *Phi)
+{
+    const double f = TWO_PI / L;
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < N; ++j) {
+        csum s = {0.0, 0.0};
+        for (int64_t i = 0; i < n_modes; ++i) {
+            const double th = f * ((double)modes[2 * i] * x[j] + (double)modes[2 * i + 1] * y[j]);
+            csum_add(&s, psi[2 * i] * cos(th) - psi[2 * i + 1] * sin(th));
+        }
+        Phi[j] = 2.0 * csum_get(&s);
+    }
+}
+
+double sce_oracle_field_energy_2d(int64_t n_modes, const int32_t *modes, const double *rho,
+                                  double L, double eps0)
+{
+    const double f = TWO_PI / L, A = L * L;
+    csum s = {0.0, 0.0};
+    for (int64_t i = 0; i < n_modes; ++i) {
+        const double kx = f * modes[2 * i], ky = f * modes[2 * i + 1];
+        const double k2 = kx * kx + ky * ky;
+        csum_add(&s, (rho[2 * i] * rho[2 * i] + rho[2 * i + 1] * rho[2 * i + 1]) / k2);
+    }
+    return csum_get(&s) / (eps0 * A);
+}
+
 /* Number of threads OpenMP will use (reported with the CPU baseline). */
 int32_t sce_oracle_threads(void)
 {

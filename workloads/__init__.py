@@ -27,6 +27,19 @@ background-neutralised plasma):
 * ``two_species``   -- neutral ion/electron plasma with mass ratio 100.
 * ``serving_requests`` -- a stream of independent small simulations with
                        log-uniform particle counts and step counts.
+
+Two-dimensional records (``dim = 2``; positions and velocities [2, N], the
+z fields are zero and unused) follow the paper's own test settings:
+
+* ``kepler_2d``     -- an electron and a "double positron" (twice the mass,
+                       twice the opposite charge) in a periodic square with
+                       tent shapes and some net linear momentum (Section 6).
+* ``thermal_2d``    -- 16 macroparticles with about 80 half-plane modes
+                       (n_max = 6: 84), the size of the paper's thermal-plasma
+                       run (Section 7; its parameter table is not
+                       self-consistent, so the physical values are not taken).
+* ``random_plasma_2d``, ``cold_lattice_2d``, ``random_particles_2d`` -- the 2-D
+                       counterparts of the 3-D generators.
 """
 from __future__ import annotations
 
@@ -39,7 +52,7 @@ ROOT_SEED = 20150828  # arXiv submission date of the paper, used as a fixed root
 
 # index of each named workload in the root seed's spawned children
 _STREAM = {"two_body": 0, "random_plasma": 1, "cold_lattice": 2,
-           "two_species": 3, "serving": 4, "misc": 5}
+           "two_species": 3, "serving": 4, "misc": 5, "two_d": 6}
 
 
 def _rng(name: str, salt: int = 0) -> np.random.Generator:
@@ -69,16 +82,21 @@ class Particles:
     dt: float = 1e-3
     n_steps: int = 1
     name: str = ""
+    dim: int = 3              # 2: line charges in the periodic square, z unused
 
     @property
     def N(self) -> int:
         return int(self.x.shape[0])
 
     def positions(self) -> np.ndarray:
-        """[3, N] float64 copy of the positions."""
+        """[dim, N] float64 copy of the positions."""
+        if self.dim == 2:
+            return np.stack([self.x, self.y]).copy()
         return np.stack([self.x, self.y, self.z]).copy()
 
     def velocities(self) -> np.ndarray:
+        if self.dim == 2:
+            return np.stack([self.vx, self.vy]).copy()
         return np.stack([self.vx, self.vy, self.vz]).copy()
 
     def copy(self) -> "Particles":
@@ -245,3 +263,107 @@ def grid_particles(G: int, L: float = 1.0, salt: int = 0) -> Particles:
     z = np.zeros(G ** 3)
     return _make(i.ravel() * L / G, j.ravel() * L / G, k.ravel() * L / G, z, z, z, q,
                  np.ones(G ** 3), L=L, name=f"grid{G}")
+
+
+# ---------------------------------------------------------------- two dimensions
+def _make2(x, y, vx, vy, q, m, **kw) -> Particles:
+    z = np.zeros(len(x))
+    return _make(x, y, z, vx, vy, z, q, m, dim=2, **kw)
+
+
+def kepler_2d(dt: float = 5e-3, n_steps: int = 2000, n_max: int = 16, a: float = 0.05,
+              L: float = 1.0) -> Particles:
+    """Line charges: an electron (q = -1, m = 1) at (0.4, 0.5) and a double
+    positron (q = +2, m = 2) at (0.6, 0.5), tent shapes of half-width a, eps0 = 1.
+    Velocities: a near-circular relative orbit for the line-charge attraction
+    |F| = |q1 q2| / (2 pi eps0 r) at r = 0.2 (relative speed 0.69, split by the
+    masses), plus a common drift (0.05, 0.02), so the total momentum is not zero."""
+    r, q1q2, mu = 0.2, 2.0, 2.0 / 3.0
+    vrel = math.sqrt(q1q2 / (2.0 * math.pi) / mu)
+    v1 = vrel * 2.0 / 3.0     # m2 / (m1 + m2)
+    v2 = -vrel * 1.0 / 3.0    # m1 / (m1 + m2)
+    dx, dy = 0.05, 0.02
+    return _make2([0.5 - r / 2, 0.5 + r / 2], [0.5, 0.5], [dx, dx], [v1 + dy, v2 + dy],
+                  [-1.0, 2.0], [1.0, 2.0], L=L, n_max=n_max, shape="tent", a=a, eps0=1.0,
+                  dt=dt, n_steps=n_steps, name="kepler_2d")
+
+
+def thermal_2d(N: int = 16, n_max: int = 6, a: float = 0.025, sigma_v: float = 0.05,
+               dt: float = 2e-3, n_steps: int = 1000, L: float = 1.0, salt: int = 0) -> Particles:
+    """Neutral thermal plasma of N line charges (alternating +/-1, unit masses),
+    uniform positions, Maxwellian velocities with std sigma_v per component."""
+    g = _rng("two_d", 100 + salt)
+    pos = g.random((2, N)) * L
+    vel = g.normal(0.0, sigma_v, (2, N))
+    q = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    return _make2(pos[0], pos[1], vel[0], vel[1], q, np.ones(N), L=L, n_max=n_max,
+                  shape="gaussian", a=a, eps0=1.0, dt=dt, n_steps=n_steps,
+                  name=f"thermal_2d_N{N}_n{n_max}")
+
+
+def random_plasma_2d(N: int = 65536, n_max: int = 32, a: float = 0.01, sigma_v: float = 0.01,
+                     dt: float = 1e-3, n_steps: int = 100, L: float = 1.0, salt: int = 0,
+                     shape: str = "gaussian", eps0: float = 1.0) -> Particles:
+    """Neutral random plasma in the square: uniform positions, charges +1 (even
+    index) and -1 (odd index), unit masses, Maxwellian velocities."""
+    g = _rng("two_d", salt)
+    pos = g.random((2, N)) * L
+    vel = g.normal(0.0, sigma_v, (2, N))
+    q = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    return _make2(pos[0], pos[1], vel[0], vel[1], q, np.ones(N), L=L, n_max=n_max,
+                  shape=shape, a=a, eps0=eps0, dt=dt, n_steps=n_steps,
+                  name=f"random_plasma_2d_N{N}_n{n_max}")
+
+
+def cold_lattice_2d(nx: int = 64, ny: int = 64, n_max: int = 8, a: float = 0.02,
+                    amplitude: float = 0.01, jitter: float = 1e-3, dt: float = 5e-3,
+                    n_steps: int = 100, L: float = 1.0, salt: int = 0, mode: int = 1) -> Particles:
+    """Cold electron plasma (q = -1, m = 1, v = 0) on an nx*ny lattice of
+    cell-centred sites in the square, each coordinate jittered uniformly in
+    [-jitter, jitter]*L, then displaced along x by -(A/k1) sin(k1 x0),
+    k1 = 2 pi mode / L (density n0 (1 + A cos(k1 x)) to first order in A)."""
+    g = _rng("two_d", 200 + salt)
+    i, j = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    x0 = (i.ravel() + 0.5) / nx * L
+    y0 = (j.ravel() + 0.5) / ny * L
+    N = x0.size
+    jit = g.uniform(-jitter, jitter, (2, N)) * L
+    x0 = x0 + jit[0]
+    y0 = y0 + jit[1]
+    k1 = 2.0 * math.pi * mode / L
+    x = x0 - (amplitude / k1) * np.sin(k1 * x0)
+    wrap = lambda u: u - L * np.floor(u / L)
+    zeros = np.zeros(N)
+    return _make2(wrap(x), wrap(y0), zeros, zeros, -np.ones(N), np.ones(N), L=L, n_max=n_max,
+                  shape="gaussian", a=a, eps0=1.0, dt=dt, n_steps=n_steps,
+                  name=f"cold_lattice_2d_{nx}x{ny}_n{n_max}")
+
+
+def random_particles_2d(N: int, L: float = 1.0, salt: int = 0, charge: str = "alternating",
+                        sigma_v: float = 0.01) -> Particles:
+    """Small 2-D particle set for parity and property tests (charges as in
+    ``random_particles``; masses uniform in [0.5, 2])."""
+    g = _rng("two_d", 300 + salt)
+    pos = g.random((2, N)) * L
+    vel = g.normal(0.0, sigma_v, (2, N))
+    if charge == "alternating":
+        q = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    elif charge == "uniform":
+        q = g.uniform(-1.0, 1.0, N)
+    elif charge == "positive":
+        q = np.ones(N)
+    else:
+        raise ValueError(charge)
+    m = g.uniform(0.5, 2.0, N)
+    return _make2(pos[0], pos[1], vel[0], vel[1], q, m, L=L, name=f"random2d_{charge}_N{N}")
+
+
+def grid_particles_2d(G: int, L: float = 1.0, salt: int = 0) -> Particles:
+    """One line charge on every site of a G^2 grid (x = L*i/G), random charges in
+    [-1, 1]; C order over (i, j)."""
+    g = _rng("two_d", 400 + salt)
+    i, j = np.meshgrid(np.arange(G), np.arange(G), indexing="ij")
+    q = g.uniform(-1.0, 1.0, G * G)
+    z = np.zeros(G * G)
+    return _make2(i.ravel() * L / G, j.ravel() * L / G, z, z, q, np.ones(G * G), L=L,
+                  name=f"grid2d_{G}")
