@@ -107,6 +107,25 @@ typedef struct {
 sce_status sce_create(double L, int32_t n_max, int32_t shape_kind, double shape_width,
                       sce_ctx *out);
 
+/* Two-dimensional context: line charges in the periodic square [0, L)^2 of
+ * area A = L^2, the setting of the paper's own test problems (Section 6, the
+ * two-body problem; Section 7, the thermal plasma).  Modes n in Z^2 with
+ * max|n_i| <= n_max, n != 0; half plane H2 = { n_x > 0 } u { n_x = 0, n_y > 0 },
+ * |H2| = ((2 n_max + 1)^2 - 1) / 2, canonical order n_x = 0..n_max, then
+ * n_y = -n_max..n_max.  The deposit, force, energies and steps are the model
+ * above with two components and A in place of V: psi_n = S(k_n) rho_n /
+ * (eps0 |k_n|^2 A), W = (1/(eps0 A)) sum_{H2} |rho|^2/|k|^2; S(k) takes the
+ * two-component k (tent: sinc^2(k_x a/2) sinc^2(k_y a/2)).  In a 2-D context
+ * every array of particle vectors (x, v, F and the checkpoint's contents as
+ * seen through sce_set_particles/sce_get_particles) is [2][N], sce_modes
+ * writes 2 ints per mode, and sce_diag.momentum[2] is 0.  Every precision
+ * and scheme is available.  Arguments and errors as for sce_create. */
+sce_status sce_create_2d(double L, int32_t n_max, int32_t shape_kind, double shape_width,
+                         sce_ctx *out);
+
+/* Spatial dimension of the context (3, or 2 for sce_create_2d). */
+sce_status sce_dimension(sce_ctx ctx, int32_t *dim);
+
 /* eps0 > 0; precision: sce_precision; scheme: sce_scheme; hip_stream: a
  * hipStream_t on the context's device, or NULL for the context's own stream.
  * Invalidates cached fields.  SCE_EINVAL on bad values. */
@@ -125,7 +144,8 @@ sce_status sce_get_particles(sce_ctx ctx, double *x, double *v, int32_t on_devic
 /* Number of stored half-space modes |H|. */
 sce_status sce_mode_count(sce_ctx ctx, int64_t *n_half);
 
-/* The stored modes in canonical order: nxyz[3*i + d] = n_d of mode i. Host memory. */
+/* The stored modes in canonical order: nxyz[3*i + d] = n_d of mode i (2 ints
+ * per mode in a 2-D context).  Host memory. */
 sce_status sce_modes(sce_ctx ctx, int32_t *nxyz);
 
 /* Deposit at the current positions: rho [2 |H|] interleaved (re, im), canonical

@@ -491,8 +491,8 @@ template <typename T, int NZC>
 __global__ void __launch_bounds__(256)
 k_force(const double *__restrict__ pos, const double *__restrict__ q,
         const double *__restrict__ m, double *__restrict__ vel, const T *__restrict__ ftab,
-        const T *__restrict__ psi0, int n, int nzp, double invL, int64_t N, double kick,
-        double *__restrict__ F, double *__restrict__ phi)
+        const T *__restrict__ psi0, int n, int lines, int nzp, double invL, int64_t N,
+        double kick, double *__restrict__ F, double *__restrict__ phi)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t jc = j < N ? j : N - 1;
@@ -523,7 +523,7 @@ k_force(const double *__restrict__ pos, const double *__restrict__ q,
             }
         }
         int r = 0;
-        for (int nx = 0; nx <= n; ++nx) {
+        for (int nx = 0; nx < lines; ++nx) {
             const int ny0 = nx == 0 ? 0 : -n;
             double hc, hs;
             cis_turns(frac_lin(nx, tx, ny0, ty), hc, hs);
@@ -588,13 +588,13 @@ hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const
     const int nzc = force_chunk(g.n, (int)sizeof(T));
     if (nzc == 8)
         hipLaunchKernelGGL((k_force<T, 8>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
-                           vel, ftab, psi0, g.n, g.nzp, 1.0 / L, N, kick, F, phi);
+                           vel, ftab, psi0, g.n, g.lines, g.nzp, 1.0 / L, N, kick, F, phi);
     else if (nzc == 16)
         hipLaunchKernelGGL((k_force<T, 16>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
-                           vel, ftab, psi0, g.n, g.nzp, 1.0 / L, N, kick, F, phi);
+                           vel, ftab, psi0, g.n, g.lines, g.nzp, 1.0 / L, N, kick, F, phi);
     else
         hipLaunchKernelGGL((k_force<T, 32>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
-                           vel, ftab, psi0, g.n, g.nzp, 1.0 / L, N, kick, F, phi);
+                           vel, ftab, psi0, g.n, g.lines, g.nzp, 1.0 / L, N, kick, F, phi);
     return hipGetLastError();
 }
 

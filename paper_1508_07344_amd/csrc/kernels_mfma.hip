@@ -634,7 +634,8 @@ hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q
 // ------------------------------------------------------------------ force table pack
 // The force visits rows in quads of 4 (one row per lane group).  Every n_x
 // line is padded to whole quads so that no quad mixes two lines: line 0
-// (n_x = 0, n_y = 0..n) has q0 quads, lines n_x = 1..n have qL quads each, and
+// (n_x = 0, n_y = 0..n) has q0 quads, lines n_x = 1..lines-1 have qL quads
+// each (lines = n + 1; a two-dimensional context has line 0 only), and
 // the row arrays are padded further to a multiple of kForceQuadAlign quads
 // (whole LDS stages of the force kernel).
 // Padding rows carry zero weights.
@@ -647,12 +648,12 @@ struct ForceQuads {
     int q0, qL, Q, Qpad;
 };
 
-__host__ __device__ inline ForceQuads force_quads(int n)
+__host__ __device__ inline ForceQuads force_quads(int n, int lines)
 {
     ForceQuads f;
     f.q0 = (n + 1 + 3) / 4;
     f.qL = (2 * n + 1 + 3) / 4;
-    f.Q = f.q0 + n * f.qL;
+    f.Q = f.q0 + (lines - 1) * f.qL;
     f.Qpad = (f.Q + kForceQuadAlign - 1) / kForceQuadAlign * kForceQuadAlign;
     return f;
 }
@@ -687,10 +688,10 @@ __host__ __device__ inline int force_row(int pr, int n, const ForceQuads &f, int
 // that psi / s stays far from overflow.  Records are stored interleaved,
 // rinfo[2 pr] = A, rinfo[2 pr + 1] = B, for 4 Qpad padded rows.
 __global__ void __launch_bounds__(256)
-k_force_rows(const float *__restrict__ ftab, const float *__restrict__ psi0, int n, int nzp,
-             float4 *__restrict__ rinfo)
+k_force_rows(const float *__restrict__ ftab, const float *__restrict__ psi0, int n, int lines,
+             int nzp, float4 *__restrict__ rinfo)
 {
-    const ForceQuads f = force_quads(n);
+    const ForceQuads f = force_quads(n, lines);
     const int pr = blockIdx.x * 256 + threadIdx.x;
     if (pr >= 4 * f.Qpad) return;
     int nx = 0, ny = 0;
@@ -721,10 +722,10 @@ k_force_rows(const float *__restrict__ ftab, const float *__restrict__ psi0, int
 // e = m % 4; K index k = 32 s + 8 (l/16) + i -> cos (k < nzk) or sin of
 // n_z = (k mod nzk) + 1.
 __global__ void __launch_bounds__(256)
-k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, int n, int nzp,
-             int nzk, int ks, _Float16 *__restrict__ wf)
+k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, int n, int lines,
+             int nzp, int nzk, int ks, _Float16 *__restrict__ wf)
 {
-    const ForceQuads f = force_quads(n);
+    const ForceQuads f = force_quads(n, lines);
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t total = (int64_t)f.Qpad * ks * 64;
     if (gid >= total) return;
@@ -765,19 +766,19 @@ k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, i
     }
 }
 
-size_t force_rowinfo_bytes(const Geom &g) { return (size_t)2 * 4 * force_quads(g.n).Qpad * sizeof(float4); }
+size_t force_rowinfo_bytes(const Geom &g) { return (size_t)2 * 4 * force_quads(g.n, g.lines).Qpad * sizeof(float4); }
 
 hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0, const Geom &g,
                              float4 *rinfo, _Float16 *wf)
 {
-    const ForceQuads f = force_quads(g.n);
+    const ForceQuads f = force_quads(g.n, g.lines);
     hipLaunchKernelGGL(k_force_rows, dim3((4 * f.Qpad + 255) / 256), dim3(256), 0, s, ftab, psi0, g.n,
-                       g.nzp, rinfo);
+                       g.lines, g.nzp, rinfo);
     const int nzk = (g.n + 15) / 16 * 16;
     const int ks = nzk / 16;
     const int64_t total = (int64_t)f.Qpad * ks * 64;
     hipLaunchKernelGGL(k_force_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ftab,
-                       rinfo, g.n, g.nzp, nzk, ks, wf);
+                       rinfo, g.n, g.lines, g.nzp, nzk, ks, wf);
     return hipGetLastError();
 }
 
@@ -827,7 +828,7 @@ template <int KS, bool PHI>
 __global__ void __launch_bounds__(64 * kForceWaves, 2)
 k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
              const double *__restrict__ m, double *__restrict__ vel, const _Float16 *__restrict__ wf,
-             const float4 *__restrict__ rinfo, int n, double invL, int64_t N, double kick,
+             const float4 *__restrict__ rinfo, int n, int lines, double invL, int64_t N, double kick,
              double *__restrict__ F, double *__restrict__ phi)
 {
     constexpr int NT = kForceNT;
@@ -845,7 +846,7 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
     const int g = lane >> 4;
     const int ln = lane & 15;
     const int nzk = 16 * KS;
-    const ForceQuads fq = force_quads(n);
+    const ForceQuads fq = force_quads(n, lines);
     const half8 *wsrc = reinterpret_cast<const half8 *>(wf);
     const half8 *isrc = reinterpret_cast<const half8 *>(rinfo);
     const int nstage = fq.Qpad / kForceTM;  // padding quads contribute zero
@@ -1015,14 +1016,15 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
 template <int KS>
 static void launch_force_ks(hipStream_t s, dim3 grid, dim3 block, const double *pos, const double *q,
                             const double *m, double *vel, const _Float16 *wf, const float4 *rinfo,
-                            int n, double invL, int64_t N, double kick, double *F, double *phi)
+                            int n, int lines, double invL, int64_t N, double kick, double *F,
+                            double *phi)
 {
     if (phi)
         hipLaunchKernelGGL((k_force_mfma<KS, true>), grid, block, 0, s, pos, q, m, vel, wf, rinfo, n,
-                           invL, N, kick, F, phi);
+                           lines, invL, N, kick, F, phi);
     else
         hipLaunchKernelGGL((k_force_mfma<KS, false>), grid, block, 0, s, pos, q, m, vel, wf, rinfo, n,
-                           invL, N, kick, F, phi);
+                           lines, invL, N, kick, F, phi);
 }
 
 hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, const double *m,
@@ -1033,10 +1035,10 @@ hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, 
     const int64_t blocks = (N + kForceBlockParticles - 1) / kForceBlockParticles;
     const dim3 grid((unsigned)blocks), block(64 * kForceWaves);
     switch (ks) {
-    case 1: launch_force_ks<1>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, 1.0 / L, N, kick, F, phi); break;
-    case 2: launch_force_ks<2>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, 1.0 / L, N, kick, F, phi); break;
-    case 3: launch_force_ks<3>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, 1.0 / L, N, kick, F, phi); break;
-    default: launch_force_ks<4>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, 1.0 / L, N, kick, F, phi); break;
+    case 1: launch_force_ks<1>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, 1.0 / L, N, kick, F, phi); break;
+    case 2: launch_force_ks<2>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, 1.0 / L, N, kick, F, phi); break;
+    case 3: launch_force_ks<3>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, 1.0 / L, N, kick, F, phi); break;
+    default: launch_force_ks<4>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, 1.0 / L, N, kick, F, phi); break;
     }
     return hipGetLastError();
 }
@@ -1044,7 +1046,7 @@ hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, 
 size_t force_pack_bytes(const Geom &g)
 {
     const int ks = (g.n + 15) / 16;
-    return (size_t)force_quads(g.n).Qpad * ks * 2 * 64 * 8 * sizeof(_Float16);
+    return (size_t)force_quads(g.n, g.lines).Qpad * ks * 2 * 64 * 8 * sizeof(_Float16);
 }
 
 }  // namespace sce

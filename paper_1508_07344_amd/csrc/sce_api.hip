@@ -34,6 +34,7 @@ struct sce_ctx_s {
     bool broken = false;
 
     double L = 1.0, width = 0.0, eps0 = 1.0;
+    int dim = 3;  // 2: line charges, stored with x = 0 and (y, z) = their (x, y)
     int kind = SCE_SHAPE_GAUSSIAN;
     int prec = SCE_PREC_FP64;
     int scheme = SCE_SCHEME_KDK;
@@ -101,13 +102,14 @@ sce_status hipfail(sce_ctx c, hipError_t e, const char *what)
         if (_e != hipSuccess) return hipfail(c, _e, #expr); \
     } while (0)
 
-Geom make_geom(int n)
+Geom make_geom(int n, int dim)
 {
     Geom g;
     g.n = n;
     g.M = 2 * n + 1;
     g.n1 = n + 1;
-    g.R = (n + 1) + n * g.M;
+    g.lines = dim == 2 ? 1 : n + 1;
+    g.R = (n + 1) + (g.lines - 1) * g.M;
     g.Rpad = (g.R + 63) / 64 * 64;
     g.P = (int64_t)g.R * g.M;
     g.H = g.P - (n + 1);
@@ -152,13 +154,17 @@ hipError_t dev_alloc(T *&p, size_t bytes)
     return e;
 }
 
-// Green tables for (row, |n_z|): S, G = S / (eps0 k^2 V), K = 1 / (eps0 k^2 V).
+// Box volume V = L^3, or the area A = L^2 of a two-dimensional context.
+double box_measure(sce_ctx c) { return c->dim == 2 ? c->L * c->L : c->L * c->L * c->L; }
+
+// Green tables for (row, |n_z|): S, G = S / (eps0 k^2 V), K = 1 / (eps0 k^2 V)
+// (V = A in two dimensions; there k_x = 0 for every stored mode).
 sce_status build_tables(sce_ctx c)
 {
     const Geom &g = c->g;
     const size_t cnt = (size_t)g.R * g.n1;
     std::vector<double> S(cnt), G(cnt), K(cnt);
-    const double f = kTwoPi / c->L, V = c->L * c->L * c->L;
+    const double f = kTwoPi / c->L, V = box_measure(c);
     double self = 0.0;
     for (int r = 0; r < g.R; ++r) {
         int nx, ny;
@@ -432,7 +438,11 @@ const char *sce_status_string(sce_status s)
 
 const char *sce_last_error(sce_ctx c) { return c ? c->err.c_str() : "null context"; }
 
-sce_status sce_create(double L, int32_t n_max, int32_t shape_kind, double shape_width, sce_ctx *out)
+}  // extern "C"
+
+namespace {
+sce_status create_ctx(double L, int32_t n_max, int32_t shape_kind, double shape_width, int dim,
+                      sce_ctx *out)
 {
     if (!out) return SCE_EINVAL;
     *out = nullptr;
@@ -445,7 +455,8 @@ sce_status sce_create(double L, int32_t n_max, int32_t shape_kind, double shape_
     c->L = L;
     c->kind = shape_kind;
     c->width = shape_width;
-    c->g = make_geom(n_max);
+    c->dim = dim;
+    c->g = make_geom(n_max, dim);
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -468,6 +479,26 @@ sce_status sce_create(double L, int32_t n_max, int32_t shape_kind, double shape_
         return st;
     }
     *out = c;
+    return SCE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+sce_status sce_create(double L, int32_t n_max, int32_t shape_kind, double shape_width, sce_ctx *out)
+{
+    return create_ctx(L, n_max, shape_kind, shape_width, 3, out);
+}
+
+sce_status sce_create_2d(double L, int32_t n_max, int32_t shape_kind, double shape_width, sce_ctx *out)
+{
+    return create_ctx(L, n_max, shape_kind, shape_width, 2, out);
+}
+
+sce_status sce_dimension(sce_ctx c, int32_t *dim)
+{
+    if (!c || !dim) return SCE_EINVAL;
+    *dim = c->dim;
     return SCE_OK;
 }
 
@@ -514,8 +545,16 @@ sce_status sce_set_particles(sce_ctx c, int64_t N, const double *x, const double
     st = ensure_particle_buffers(c, N);
     if (st) return st;
     c->N = N;
-    if ((st = copy_in(c, c->pos, x, 3 * N * sizeof(double), on_device))) return st;
-    if ((st = copy_in(c, c->vel, v, 3 * N * sizeof(double), on_device))) return st;
+    if (c->dim == 2) {
+        // [2][N] in, stored as (0, x, y)
+        HIPCHK(c, hipMemsetAsync(c->pos, 0, N * sizeof(double), c->stream));
+        HIPCHK(c, hipMemsetAsync(c->vel, 0, N * sizeof(double), c->stream));
+        if ((st = copy_in(c, c->pos + N, x, 2 * N * sizeof(double), on_device))) return st;
+        if ((st = copy_in(c, c->vel + N, v, 2 * N * sizeof(double), on_device))) return st;
+    } else {
+        if ((st = copy_in(c, c->pos, x, 3 * N * sizeof(double), on_device))) return st;
+        if ((st = copy_in(c, c->vel, v, 3 * N * sizeof(double), on_device))) return st;
+    }
     if ((st = copy_in(c, c->q, q, N * sizeof(double), on_device))) return st;
     if ((st = copy_in(c, c->m, m, N * sizeof(double), on_device))) return st;
     HIPCHK(c, sce::launch_wrap(c->stream, c->pos, N, c->L));
@@ -541,8 +580,10 @@ sce_status sce_get_particles(sce_ctx c, double *x, double *v, int32_t on_device)
     sce_status st = check_ready(c);
     if (st) return st;
     if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
-    if (x && (st = copy_out(c, x, c->pos, 3 * c->N * sizeof(double), on_device))) return st;
-    if (v && (st = copy_out(c, v, c->vel, 3 * c->N * sizeof(double), on_device))) return st;
+    const int64_t off = c->dim == 2 ? c->N : 0;
+    const size_t bytes = (size_t)c->dim * c->N * sizeof(double);
+    if (x && (st = copy_out(c, x, c->pos + off, bytes, on_device))) return st;
+    if (v && (st = copy_out(c, v, c->vel + off, bytes, on_device))) return st;
     return SCE_OK;
 }
 
@@ -563,9 +604,14 @@ sce_status sce_modes(sce_ctx c, int32_t *nxyz)
         sce::row_nxny(r, g.n, nx, ny);
         for (int nz = -g.n; nz <= g.n; ++nz) {
             if (!sce::in_half(nx, ny, nz)) continue;
-            nxyz[3 * i] = nx;
-            nxyz[3 * i + 1] = ny;
-            nxyz[3 * i + 2] = nz;
+            if (c->dim == 2) {
+                nxyz[2 * i] = ny;
+                nxyz[2 * i + 1] = nz;
+            } else {
+                nxyz[3 * i] = nx;
+                nxyz[3 * i + 1] = ny;
+                nxyz[3 * i + 2] = nz;
+            }
             ++i;
         }
     }
@@ -597,7 +643,9 @@ sce_status sce_force(sce_ctx c, double *F, int32_t on_device)
     if (st) return st;
     if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
     if ((st = pass(c, 0.0))) return st;
-    if (F) return copy_out(c, F, c->F, 3 * c->N * sizeof(double), on_device);
+    if (F)
+        return copy_out(c, F, c->F + (c->dim == 2 ? c->N : 0), (size_t)c->dim * c->N * sizeof(double),
+                        on_device);
     return SCE_OK;
 }
 
@@ -642,21 +690,27 @@ sce_status sce_diagnostics(sce_ctx c, sce_diag *out, double *rho_abs)
     c->dscratch = (double *)ds;
     if (st) return st;
     HIPCHK(c, sce::launch_diag(c->stream, c->vel, c->q, c->m, c->phi, c->N, c->wpart, c->wblocks,
-                               c->eps0 * c->L * c->L * c->L, c->dscratch, c->dout));
+                               c->eps0 * box_measure(c), c->dscratch, c->dout));
     double h[8];
     HIPCHK(c, hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     out->step = c->step;
     out->time = c->time;
     out->kinetic = h[0];
-    out->momentum[0] = h[1];
-    out->momentum[1] = h[2];
-    out->momentum[2] = h[3];
+    if (c->dim == 2) {
+        out->momentum[0] = h[2];
+        out->momentum[1] = h[3];
+        out->momentum[2] = 0.0;
+    } else {
+        out->momentum[0] = h[1];
+        out->momentum[1] = h[2];
+        out->momentum[2] = h[3];
+    }
     out->momentum_abs_sum = h[4];
     out->interaction = h[5];
     out->field = h[6];
     out->rho_abs_max = h[7];
-    out->field_self = c->q2sum / (c->eps0 * c->L * c->L * c->L) * c->self_sum;
+    out->field_self = c->q2sum / (c->eps0 * box_measure(c)) * c->self_sum;
     out->total = out->kinetic + out->field;
     if (rho_abs) {
         std::vector<double2> r(c->g.H);
@@ -678,8 +732,10 @@ struct StateHeader {
     double L;
     int32_t n_max;
     int32_t has_force;
+    int32_t dim;
+    int32_t reserved;
 };
-const uint64_t kMagic = 0x31454353484b5053ull;  // "SPKHSCE1"
+const uint64_t kMagic = 0x32454353484b5053ull;  // "SPKHSCE2"
 }  // namespace
 
 sce_status sce_get_state(sce_ctx c, void *buf, size_t *bytes)
@@ -694,7 +750,7 @@ sce_status sce_get_state(sce_ctx c, void *buf, size_t *bytes)
         return SCE_OK;
     }
     if (*bytes < need) return fail(c, SCE_EINVAL, "buffer too small");
-    StateHeader hd{kMagic, c->N, c->step, c->time, c->L, c->g.n, c->force_valid ? 1 : 0};
+    StateHeader hd{kMagic, c->N, c->step, c->time, c->L, c->g.n, c->force_valid ? 1 : 0, c->dim, 0};
     std::memcpy(buf, &hd, sizeof(hd));
     double *d = (double *)((char *)buf + sizeof(hd));
     const size_t n3 = 3 * c->N * sizeof(double), n1 = c->N * sizeof(double);
@@ -715,12 +771,14 @@ sce_status sce_set_state(sce_ctx c, const void *buf, size_t bytes)
     if (!buf || bytes < sizeof(StateHeader)) return fail(c, SCE_EINVAL, "bad checkpoint");
     StateHeader hd;
     std::memcpy(&hd, buf, sizeof(hd));
-    if (hd.magic != kMagic || hd.N < 1 || hd.L != c->L || hd.n_max != c->g.n ||
+    if (hd.magic != kMagic || hd.N < 1 || hd.L != c->L || hd.n_max != c->g.n || hd.dim != c->dim ||
         bytes < sizeof(hd) + (size_t)hd.N * 11 * sizeof(double))
         return fail(c, SCE_EINVAL, "checkpoint does not match this context");
     const double *d = (const double *)((const char *)buf + sizeof(hd));
     const int64_t N = hd.N;
-    if ((st = sce_set_particles(c, N, d, d + 3 * N, d + 6 * N, d + 7 * N, 0))) return st;
+    // the arrays are stored as (x, y, z); a 2-D context takes its (x, y) = stored (y, z)
+    const int64_t off = c->dim == 2 ? N : 0;
+    if ((st = sce_set_particles(c, N, d + off, d + 3 * N + off, d + 6 * N, d + 7 * N, 0))) return st;
     if (hd.has_force) {
         if ((st = copy_in(c, c->F, d + 8 * N, 3 * N * sizeof(double), 0))) return st;
         c->force_valid = true;

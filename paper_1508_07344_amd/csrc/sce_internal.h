@@ -6,6 +6,10 @@
 //   rows 0..n        : n_x = 0, n_y = r            (n_y < 0 at n_x = 0 lies in -H)
 //   rows n+1..R-1    : n_x = 1 + (r-n-1) / M, n_y = (r-n-1) % M - n
 //   R = (n+1) + n M, M = 2n+1; padded mode p = r M + (n_z + n), P = R M.
+// A two-dimensional context (line charges, modes (m_x, m_y)) keeps only rows
+// 0..n: its half plane {m_x > 0} u {m_x = 0, m_y > 0} is the n_x = 0 slice of
+// H with (n_y, n_z) = (m_x, m_y), so its particles are stored with x = 0 and
+// (y, z) = their (x, y), and R = n + 1.
 // Row 0 holds n_z = -n..0, which are not in H (0 and the negatives of row 0's
 // positive half); everything else is in H, so the canonical mode index is
 // simply p - (n+1).
@@ -24,6 +28,7 @@ struct Geom {
     int Rpad;    // rows rounded up to 64
     int64_t P;   // padded modes R*M
     int64_t H;   // |H| = P - (n+1)
+    int lines;   // n_x lines of the row layout: n + 1 in 3-D, 1 in 2-D (rows 0..n only)
     int nzp;     // n_z slots of the force table (n rounded up to the force chunk)
     int zslots;  // n_z slots (0..zslots-1) of the per-particle phase table, >= n+1
 };

@@ -99,6 +99,8 @@ def load_library():
     P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
         "sce_create": ([f64, i32, i32, f64, ctypes.POINTER(P)], i32),
+        "sce_create_2d": ([f64, i32, i32, f64, ctypes.POINTER(P)], i32),
+        "sce_dimension": ([P, ctypes.POINTER(i32)], i32),
         "sce_set_options": ([P, f64, i32, i32, P], i32),
         "sce_set_particles": ([P, i64, P, P, P, P, i32], i32),
         "sce_get_particles": ([P, P, P, i32], i32),
@@ -163,16 +165,21 @@ def _ptr(a):
 
 
 class Context:
-    """One simulation context (``sce_ctx``)."""
+    """One simulation context (``sce_ctx``); ``dim`` = 2 makes a two-dimensional
+    one (``sce_create_2d``), whose particle vectors are [2, N]."""
 
-    def __init__(self, L: float, n_max: int, shape: str = "gaussian", width: float = 0.0):
+    def __init__(self, L: float, n_max: int, shape: str = "gaussian", width: float = 0.0,
+                 dim: int = 3):
         self._lib = load_library()
         h = ctypes.c_void_p()
-        st = self._lib.sce_create(float(L), int(n_max), SHAPE[shape], float(width), ctypes.byref(h))
+        if dim not in (2, 3):
+            raise ValueError("dim must be 2 or 3")
+        create = self._lib.sce_create_2d if dim == 2 else self._lib.sce_create
+        st = create(float(L), int(n_max), SHAPE[shape], float(width), ctypes.byref(h))
         if st != SCE_OK:
             raise SceError(st, "sce_create: " + self._lib.sce_status_string(st).decode())
         self._h = h
-        self.L, self.n_max, self.N = float(L), int(n_max), 0
+        self.L, self.n_max, self.N, self.dim = float(L), int(n_max), 0, int(dim)
 
     def _chk(self, st: int, what: str):
         if st != SCE_OK:
@@ -203,8 +210,13 @@ class Context:
         self._chk(self._lib.sce_set_options(self._h, float(eps0), PREC[precision], SCHEME[scheme], s),
                   "sce_set_options")
 
+    def sce_dimension(self) -> int:
+        d = ctypes.c_int32()
+        self._chk(self._lib.sce_dimension(self._h, ctypes.byref(d)), "sce_dimension")
+        return int(d.value)
+
     def sce_set_particles(self, x, v, q, m):
-        """x, v: [3, N]; q, m: [N]; numpy (host) or torch CUDA tensors (device)."""
+        """x, v: [dim, N]; q, m: [N]; numpy (host) or torch CUDA tensors (device)."""
         N = int(q.shape[0])
         px, dx = _ptr(x)
         pv, dv = _ptr(v)
@@ -220,8 +232,8 @@ class Context:
 
     def sce_get_particles(self, x=None, v=None):
         if x is None and v is None:
-            x = np.zeros((3, self.N))
-            v = np.zeros((3, self.N))
+            x = np.zeros((self.dim, self.N))
+            v = np.zeros((self.dim, self.N))
         px, dx = _ptr(x) if x is not None else (None, 0)
         pv, dv = _ptr(v) if v is not None else (None, dx)
         _torch_sync_if_device(x, v)
@@ -236,7 +248,7 @@ class Context:
         return int(n.value)
 
     def sce_modes(self) -> np.ndarray:
-        out = np.zeros((self.sce_mode_count(), 3), dtype=np.int32)
+        out = np.zeros((self.sce_mode_count(), self.dim), dtype=np.int32)
         self._chk(self._lib.sce_modes(self._h, _host(out)), "sce_modes")
         return out
 
@@ -259,9 +271,9 @@ class Context:
         return buf[0::2] + 1j * buf[1::2]
 
     def sce_force(self, out=None):
-        """Returns F [3, N] float64 (host) unless ``out`` is given."""
+        """Returns F [dim, N] float64 (host) unless ``out`` is given."""
         if out is None:
-            buf = np.zeros((3, self.N))
+            buf = np.zeros((self.dim, self.N))
             self._chk(self._lib.sce_force(self._h, _host(buf), 0), "sce_force")
             return buf
         p, d = _ptr(out)
@@ -296,7 +308,7 @@ class Context:
     def sce_set_state(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._chk(self._lib.sce_set_state(self._h, buf, len(blob)), "sce_set_state")
-        self.N = (len(blob) - 48) // (11 * 8)
+        self.N = int(np.frombuffer(blob[8:16], dtype=np.int64)[0])  # header: magic, N, ...
 
     def sce_sync(self):
         self._chk(self._lib.sce_sync(self._h), "sce_sync")
@@ -316,7 +328,7 @@ class Context:
     @classmethod
     def from_particles(cls, p, precision: str = "fp64", scheme: str = "kdk", device: bool = False):
         """Context for a ``workloads.Particles`` record, particles already set."""
-        c = cls(p.L, p.n_max, p.shape, p.a)
+        c = cls(p.L, p.n_max, p.shape, p.a, dim=getattr(p, "dim", 3))
         c.sce_set_options(p.eps0, precision, scheme)
         if device:
             import torch
