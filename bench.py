@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -52,10 +53,12 @@ def parse():
                     help="requests of the serving workload (0 = skip the serving run)")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load as a fraction of the measured saturated capacity")
-    ap.add_argument("--study", default="", choices=["", "longrun", "dispersion", "h2"],
+    ap.add_argument("--study", default="", choices=["", "longrun", "dispersion", "h2", "twod"],
                     help="run one validation study instead of the throughput benchmark")
     ap.add_argument("--long-steps", type=int, default=100000,
                     help="steps of the long-run conservation study")
+    ap.add_argument("--twod-steps", type=int, default=200000,
+                    help="steps of each long run of the two-dimensional study")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device-to-device copy of this many MiB (five times), "
                          "the reference kernel for scaling the FETCH_SIZE/WRITE_SIZE counters")
@@ -364,6 +367,88 @@ def study_longrun(sce, steps, every=1000):
                         "sigma_v = 0.02, h = 1e-3, KDK", "results": res}
 
 
+def _energy_series(c, h, steps, every):
+    """Run ``steps`` steps of size h, sampling the diagnostics every ``every``
+    steps: returns (steps, E, K, W, momentum error relative to sum m|v|)."""
+    import numpy as np
+    d = c.sce_diagnostics()[0]
+    P0 = np.array(d.momentum)
+    ts, Es, Ks, Ws, perr = [0], [d.total], [d.kinetic], [d.field], [0.0]
+    for i in range(steps // every):
+        c.sce_step(h, every)
+        d = c.sce_diagnostics()[0]
+        ts.append((i + 1) * every)
+        Es.append(d.total)
+        Ks.append(d.kinetic)
+        Ws.append(d.field)
+        perr.append(float(np.max(np.abs(np.array(d.momentum) - P0)) / d.momentum_abs_sum))
+    return np.array(ts), np.array(Es), np.array(Ks), np.array(Ws), np.array(perr)
+
+
+def study_twod(sce, steps):
+    """The paper's own two-dimensional settings (FP64, KDK), line charges in
+    the unit periodic square:
+    * Kepler problem (Section 6): an electron and a double positron, tent
+      shapes, delta field shape, net linear momentum; at about 10 steps per
+      orbit (the paper's resolution) and at 100, energy sampled every 250
+      steps: relative energy deviation after the first 5% of the run (the
+      transient), the kinetic and field parts, the momentum error; and the
+      largest energy deviation over two orbits against h (slope 2).
+    * Thermal plasma (Section 7): 16 line charges, n_max = 6 (84 modes), the
+      paper's ratios L = 4 lambda_D and width 0.1 lambda_D, k_max sigma_v h = 0.1:
+      energy deviation and momentum error over the run."""
+    import numpy as np
+    import workloads
+    out = {"study": "twod"}
+    p0 = workloads.kepler_2d()
+    T_orbit = 2.0 * math.pi * 0.2 / math.sqrt(2.0 / (2.0 * math.pi) / (2.0 / 3.0))
+    kep = []
+    for per_orbit in (10, 100):
+        h = T_orbit / per_orbit
+        with sce.Context.from_particles(p0.with_(dt=h), precision="fp64") as c:
+            t0 = time.perf_counter()
+            ts, Es, Ks, Ws, perr = _energy_series(c, h, steps, 250)
+            wall = time.perf_counter() - t0
+        late = ts >= 0.05 * ts[-1]
+        kep.append({"steps_per_orbit": per_orbit, "h": h, "steps": int(ts[-1]),
+                    "orbits": float(ts[-1] / per_orbit), "ms_per_step": 1e3 * wall / ts[-1],
+                    "E0": float(Es[0]),
+                    "max_dE_rel": float(np.max(np.abs(Es - Es[0])) / abs(Es[0])),
+                    "max_dE_rel_after_transient": float(np.max(np.abs(Es[late] - np.mean(Es[late]))) / abs(Es[0])),
+                    "drift_rel_per_1e5_steps": float(np.polyfit(ts[late], Es[late], 1)[0]) * 1e5 / abs(Es[0]),
+                    "K_range": [float(Ks.min()), float(Ks.max())], "W_range": [float(Ws.min()), float(Ws.max())],
+                    "momentum_err_max": float(np.max(perr))})
+        print(f"kepler2d {per_orbit}/orbit done", file=sys.stderr, flush=True)
+    out["kepler"] = kep
+    rows = []
+    for per_orbit in (20, 40, 80, 160, 320):
+        h = T_orbit / per_orbit
+        with sce.Context.from_particles(p0.with_(dt=h), precision="fp64") as c:
+            E0 = c.sce_diagnostics()[0].total
+            dev = 0.0
+            for _ in range(2 * per_orbit):
+                c.sce_step(h, 1)
+                dev = max(dev, abs(c.sce_diagnostics()[0].total - E0))
+        rows.append({"h": h, "max_dE": dev})
+    slope = float(np.polyfit(np.log([r["h"] for r in rows]), np.log([r["max_dE"] for r in rows]), 1)[0])
+    out["kepler_h2"] = {"rows": rows, "slope": slope}
+    pt = workloads.thermal_2d()
+    wp = math.sqrt(pt.N / pt.L ** 2)
+    h = pt.dt
+    with sce.Context.from_particles(pt, precision="fp64") as c:
+        ts, Es, Ks, Ws, perr = _energy_series(c, h, steps, 250)
+    out["thermal"] = {"N": pt.N, "n_max": pt.n_max, "modes": (pt.n_max * 2 + 1) ** 2 // 2,
+                      "omega_p_h": wp * h, "L_over_lambda_D": 4.0, "steps": int(ts[-1]),
+                      "plasma_periods": float(ts[-1] * h * wp / (2 * math.pi)),
+                      "E0": float(Es[0]), "max_dE_rel": float(np.max(np.abs(Es - Es[0])) / abs(Es[0])),
+                      "drift_rel_per_1e5_steps": float(np.polyfit(ts, Es, 1)[0]) * 1e5 / abs(Es[0]),
+                      "momentum_err_max": float(np.max(perr))}
+    out["workload"] = ("kepler_2d (q = -1, m = 1 and q = +2, m = 2, r = 0.2, tent a = 0.05, n_max = 16), "
+                       "thermal_2d (16 line charges, L = 4 lambda_D, Gaussian a = 0.1 lambda_D, n_max = 6, "
+                       "k_max sigma_v h = 0.1), unit square, FP64 KDK")
+    return out
+
+
 def cpu_baseline(p, sample):
     import numpy as np
     import oracle
@@ -399,6 +484,8 @@ def main():
             r = study_longrun(sce, a.long_steps)
         elif a.study == "dispersion":
             r = study_dispersion(sce)
+        elif a.study == "twod":
+            r = study_twod(sce, a.twod_steps)
         else:
             r = study_h2(sce)
         print(json.dumps(r), flush=True)

@@ -36,8 +36,9 @@ z fields are zero and unused) follow the paper's own test settings:
                        tent shapes and some net linear momentum (Section 6).
 * ``thermal_2d``    -- 16 macroparticles with about 80 half-plane modes
                        (n_max = 6: 84), the size of the paper's thermal-plasma
-                       run (Section 7; its parameter table is not
-                       self-consistent, so the physical values are not taken).
+                       run (Section 7), with its stated ratios L = 4 lambda_D and
+                       width 0.1 lambda_D; its time step and its table's
+                       physical values are not self-consistent and are not taken.
 * ``random_plasma_2d``, ``cold_lattice_2d``, ``random_particles_2d`` -- the 2-D
                        counterparts of the 3-D generators.
 """
@@ -288,10 +289,20 @@ def kepler_2d(dt: float = 5e-3, n_steps: int = 2000, n_max: int = 16, a: float =
                   dt=dt, n_steps=n_steps, name="kepler_2d")
 
 
-def thermal_2d(N: int = 16, n_max: int = 6, a: float = 0.025, sigma_v: float = 0.05,
-               dt: float = 2e-3, n_steps: int = 1000, L: float = 1.0, salt: int = 0) -> Particles:
-    """Neutral thermal plasma of N line charges (alternating +/-1, unit masses),
-    uniform positions, Maxwellian velocities with std sigma_v per component."""
+def thermal_2d(N: int = 16, n_max: int = 6, L: float = 1.0, n_steps: int = 1000,
+               salt: int = 0) -> Particles:
+    """Neutral thermal plasma of N line charges (alternating +/-1, unit masses,
+    eps0 = 1), uniform positions, Maxwellian velocities, with the ratios the
+    paper states for its thermal run (Section 7): box L = 4 Debye lengths and
+    particle width 0.1 Debye length.  With omega_p^2 = N / L^2: lambda_D = L/4,
+    sigma_v = omega_p lambda_D per component, Gaussian a = 0.1 lambda_D.  The
+    paper's step, a fifth of a plasma period, lets a thermal particle cross
+    the shortest retained wavelength twice per step (k_max sigma_v h = 12); the
+    step here keeps k_max sigma_v h = 0.1."""
+    wp = math.sqrt(N) / L
+    lam = L / 4.0
+    sigma_v, a = wp * lam, 0.1 * lam
+    dt = 0.1 / (2.0 * math.pi * n_max / L * sigma_v)
     g = _rng("two_d", 100 + salt)
     pos = g.random((2, N)) * L
     vel = g.normal(0.0, sigma_v, (2, N))
