@@ -159,8 +159,18 @@ sce_status sce_psi(sce_ctx ctx, double *psi, int32_t on_device);
  * Velocities are not changed.  F may be NULL. */
 sce_status sce_force(sce_ctx ctx, double *F, int32_t on_device);
 
-/* Advance n_steps >= 0 steps of size dt (finite) with the configured scheme. */
+/* Advance n_steps >= 0 steps of size dt (finite) with the configured scheme.
+ * With n_steps >= 2 G (G = steps per graph, see sce_set_step_graph) and
+ * timing off, the first step runs directly, then blocks of G steps replay a
+ * HIP graph of their launches (captured again whenever dt, the scheme, the
+ * particles or the options change), then the rest run directly.  Results are
+ * identical to launching every step directly. */
 sce_status sce_step(sce_ctx ctx, double dt, int64_t n_steps);
+
+/* Steps per captured graph for sce_step, 0..4096 (0: launch every step
+ * directly; default 8).  Replaying a graph removes the host's per-launch
+ * cost and the gaps between kernels.  SCE_EINVAL outside the range. */
+sce_status sce_set_step_graph(sce_ctx ctx, int32_t steps_per_graph);
 
 /* Diagnostics at the current state; rho_abs (|H| doubles, host) may be NULL.
  * Runs a deposit if the fields are not current.  Returns SCE_EUNSTABLE (with

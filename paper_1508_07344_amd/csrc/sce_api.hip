@@ -72,6 +72,18 @@ struct sce_ctx_s {
     double q2sum = 0.0;
     double self_sum = 0.0;  // sum_H S^2 / |k|^2
 
+    // Multi-step runs replay a captured HIP graph of graph_steps steps (0: launch
+    // directly).  gen counts every change of a buffer, a kernel argument fixed
+    // at capture or the stream; the graph is captured again when gen, dt or the
+    // scheme differ from what it was captured with.
+    int graph_steps = 8;
+    uint64_t gen = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    uint64_t g_gen = 0;
+    double g_dt = 0.0;
+    int g_scheme = -1, g_len = 0;
+
     bool timing = false;
     std::vector<EventPair> ev_dep, ev_frc;
     std::vector<hipEvent_t> ev_pool;
@@ -201,6 +213,7 @@ sce_status build_tables(sce_ctx c)
 // Buffers whose size depends on the precision (force table, psi0).
 sce_status alloc_prec_buffers(sce_ctx c)
 {
+    c->gen++;
     free_dev(c->ftab);
     free_dev(c->psi0);
     const size_t eb = elem_bytes(c->prec == SCE_PREC_FP64 ? SCE_PREC_FP64 : SCE_PREC_FP32);
@@ -220,6 +233,7 @@ sce_status alloc_prec_buffers(sce_ctx c)
 sce_status ensure_particle_buffers(sce_ctx c, int64_t N)
 {
     if (N <= c->cap) return SCE_OK;
+    c->gen++;
     free_devp(c->pos);
     free_devp(c->vel);
     free_devp(c->q);
@@ -239,6 +253,7 @@ sce_status ensure_particle_buffers(sce_ctx c, int64_t N)
 sce_status ensure_bytes(sce_ctx c, void *&p, size_t &have, size_t need)
 {
     if (need <= have) return SCE_OK;
+    c->gen++;
     free_dev(p);
     have = 0;
     HIPCHK(c, hipMalloc(&p, need));
@@ -532,6 +547,7 @@ sce_status sce_set_options(sce_ctx c, double eps0, int32_t precision, int32_t sc
         c->tab_bytes = 0;
     }
     c->fields_valid = c->force_valid = false;
+    c->gen++;  // precision, stream and tables are captured by a step graph
     return SCE_OK;
 }
 
@@ -569,6 +585,7 @@ sce_status sce_set_particles(sce_ctx c, int64_t N, const double *x, const double
     }
     c->q2sum = s;
     c->qscale = qmax > 0.0 ? qmax : 1.0;
+    c->gen++;  // N, qscale and the particle buffers are captured by a step graph
     c->step = 0;
     c->time = 0.0;
     c->fields_valid = c->force_valid = false;
@@ -649,6 +666,88 @@ sce_status sce_force(sce_ctx c, double *F, int32_t on_device)
     return SCE_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One leapfrog step: its launches on the context's stream.
+sce_status step_once(sce_ctx c, double dt)
+{
+    sce_status st;
+    if (c->scheme == SCE_SCHEME_KDK) {
+        if (!c->force_valid && (st = pass(c, 0.0))) return st;
+        HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
+                                         0.5 * dt, dt));
+        c->fields_valid = c->force_valid = false;
+        if ((st = pass(c, 0.5 * dt))) return st;
+    } else {
+        HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
+                                         0.0, 0.5 * dt));
+        if ((st = pass(c, dt))) return st;
+        HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
+                                         0.0, 0.5 * dt));
+        c->fields_valid = c->force_valid = false;
+    }
+    c->step += 1;
+    c->time += dt;
+    return SCE_OK;
+}
+
+void drop_graph(sce_ctx c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->g_len = 0;
+}
+
+// Capture graph_steps steps of size dt into an executable graph.  The steps
+// must have run once already (every buffer exists, the KDK force is
+// current), so the captured launches are exactly those of a replayed step.
+// No memset and no host synchronisation is recorded: a step is kernel
+// launches only.
+sce_status capture_steps(sce_ctx c, double dt)
+{
+    drop_graph(c);
+    const int64_t step0 = c->step;
+    const double time0 = c->time;
+    const bool fv = c->fields_valid, cv = c->force_valid, pv = c->phi_valid;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    sce_status st = SCE_OK;
+    for (int i = 0; i < c->graph_steps && !st; ++i) st = step_once(c, dt);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->step = step0;
+    c->time = time0;
+    // flags as after the captured steps; restored if the capture fails
+    if (st || e != hipSuccess) {
+        c->fields_valid = fv;
+        c->force_valid = cv;
+        c->phi_valid = pv;
+        if (g) (void)hipGraphDestroy(g);
+        if (st) return st;
+        return hipfail(c, e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hipfail(c, ei, "hipGraphInstantiate");
+    }
+    c->graph = g;
+    c->gexec = x;
+    c->g_gen = c->gen;
+    c->g_dt = dt;
+    c->g_scheme = c->scheme;
+    c->g_len = c->graph_steps;
+    return SCE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 sce_status sce_step(sce_ctx c, double dt, int64_t n_steps)
 {
     sce_status st = check_ready(c);
@@ -656,24 +755,35 @@ sce_status sce_step(sce_ctx c, double dt, int64_t n_steps)
     if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
     if (!std::isfinite(dt)) return fail(c, SCE_EINVAL, "dt must be finite");
     if (n_steps < 0) return fail(c, SCE_EINVAL, "n_steps must be >= 0");
-    for (int64_t s = 0; s < n_steps; ++s) {
-        if (c->scheme == SCE_SCHEME_KDK) {
-            if (!c->force_valid && (st = pass(c, 0.0))) return st;
-            HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
-                                             0.5 * dt, dt));
-            c->fields_valid = c->force_valid = false;
-            if ((st = pass(c, 0.5 * dt))) return st;
-        } else {
-            HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
-                                             0.0, 0.5 * dt));
-            if ((st = pass(c, dt))) return st;
-            HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
-                                             0.0, 0.5 * dt));
-            c->fields_valid = c->force_valid = false;
+    int64_t s = 0;
+    const int G = c->graph_steps;
+    if (G > 0 && !c->timing && n_steps >= 2 * (int64_t)G) {
+        if ((st = step_once(c, dt))) return st;
+        ++s;
+        if (!(c->gexec && c->g_gen == c->gen && c->g_dt == dt && c->g_scheme == c->scheme &&
+              c->g_len == G)) {
+            if ((st = capture_steps(c, dt))) return st;
         }
-        c->step += 1;
-        c->time += dt;
+        for (; n_steps - s >= G; s += G) {
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+            c->step += G;
+            c->time += G * dt;
+        }
     }
+    for (; s < n_steps; ++s)
+        if ((st = step_once(c, dt))) return st;
+    return SCE_OK;
+}
+
+sce_status sce_set_step_graph(sce_ctx c, int32_t steps_per_graph)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (steps_per_graph < 0 || steps_per_graph > 4096)
+        return fail(c, SCE_EINVAL, "steps_per_graph must be in 0..4096");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->graph_steps = steps_per_graph;
     return SCE_OK;
 }
 
@@ -841,6 +951,7 @@ void sce_destroy(sce_ctx c)
     for (auto &p : c->ev_dep) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto &p : c->ev_frc) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    drop_graph(c);
     free_devp(c->pos);
     free_devp(c->vel);
     free_devp(c->q);
