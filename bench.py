@@ -57,6 +57,8 @@ def parse():
                     help="run one validation study instead of the throughput benchmark")
     ap.add_argument("--long-steps", type=int, default=100000,
                     help="steps of the long-run conservation study")
+    ap.add_argument("--long-precisions", default="split_f16,fp32,fp64",
+                    help="comma list of precisions of the long-run study")
     ap.add_argument("--twod-steps", type=int, default=200000,
                     help="steps of each long run of the two-dimensional study")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -328,7 +330,7 @@ def study_h2(sce):
             "rows": out, "slope_max_dE": slope, "slope_max_step_dE": slope1}
 
 
-def study_longrun(sce, steps, every=1000):
+def study_longrun(sce, steps, every=1000, precisions=("split_f16", "fp32", "fp64")):
     """Two-species neutral plasma, N = 262,144, n_max = 16, h = 1e-3: relative
     energy drift per 1,000 steps (least-squares slope over the second half of the
     run, relative to |E0| and to the mean kinetic energy there) and the largest
@@ -337,7 +339,7 @@ def study_longrun(sce, steps, every=1000):
     import workloads
     p = workloads.two_species()
     res = {}
-    for prec in ["split_f16", "fp32", "fp64"]:
+    for prec in precisions:
         with sce.Context.from_particles(p, precision=prec, scheme="kdk") as c:
             d = c.sce_diagnostics()[0]
             P0 = np.array(d.momentum)
@@ -481,7 +483,7 @@ def main():
         sys.exit(1)
     if a.study:
         if a.study == "longrun":
-            r = study_longrun(sce, a.long_steps)
+            r = study_longrun(sce, a.long_steps, precisions=[x for x in a.long_precisions.split(",") if x])
         elif a.study == "dispersion":
             r = study_dispersion(sce)
         elif a.study == "twod":
