@@ -579,11 +579,115 @@ k_force(const double *__restrict__ pos, const double *__restrict__ q,
     }
 }
 
+// Small particle counts: one block of 256 threads per particle, the rows split
+// across the threads (thread t takes rows t, t + 256, ...), so that a step of a
+// handful of particles is not one serial mode sum per particle.  The
+// particle's cos/sin(n_z tz), n_z = 1..n, are formed once per block in LDS,
+// each from its own FP64 anchor; each row's phase exp(2 pi i (n_x tx + n_y ty))
+// is an FP64 anchor too.  The threads' FP64 sums are combined in a fixed
+// order, so the result does not depend on scheduling.  Up to these counts it
+// is faster than one particle per lane, which leaves most compute units idle
+// below a few hundred blocks (measured crossover between 8K and 16K particles
+// in FP32, above 16K in FP64, for n_max 8 to 32).
+template <typename T> constexpr int64_t force_small_max() { return sizeof(T) == 8 ? 16384 : 8192; }
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_force_small(const double *__restrict__ pos, const double *__restrict__ q,
+              const double *__restrict__ m, double *__restrict__ vel, const T *__restrict__ ftab,
+              const T *__restrict__ psi0, int n, int R, int nzp, double invL, int64_t N,
+              double kick, double *__restrict__ F, double *__restrict__ phi)
+{
+    __shared__ T csz[2][64];  // cos, sin(n_z tz) for n_z = 1..n (n <= 64)
+    __shared__ double red[4][256];
+    const int64_t j = blockIdx.x;
+    const int t = threadIdx.x;
+    const double tx = frac(pos[j] * invL);
+    const double ty = frac(pos[N + j] * invL);
+    const double tz = frac(pos[2 * N + j] * invL);
+    if (t < n) {
+        double c, sn;
+        cis_turns(frac_mul(t + 1, tz), c, sn);
+        csz[0][t] = (T)c;
+        csz[1][t] = (T)sn;
+    }
+    __syncthreads();
+    double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
+    for (int r = t; r < R; r += 256) {
+        int nx, ny;
+        row_nxny(r, n, nx, ny);
+        double hc, hs;
+        cis_turns(frac_lin(nx, tx, ny, ty), hc, hs);
+        const T *ft = ftab + (int64_t)r * nzp * 8;
+        double U0r = (double)psi0[2 * r], U0i = (double)psi0[2 * r + 1], U1r = 0.0, U1i = 0.0;
+        // Sums over n_z in chunks of 16 in T, each chunk added in FP64.
+        for (int k0 = 0; k0 < n; k0 += 16) {
+            const int k1 = k0 + 16 < n ? k0 + 16 : n;
+            T u0r = (T)0, u0i = (T)0, u1r = (T)0, u1i = (T)0;
+            for (int k = k0; k < k1; ++k) {
+                const T c = csz[0][k], sn = csz[1][k];
+                u0r = fma(ft[8 * k + 0], c, u0r);
+                u0i = fma(ft[8 * k + 1], c, u0i);
+                u0r = fma(-ft[8 * k + 3], sn, u0r);
+                u0i = fma(ft[8 * k + 2], sn, u0i);
+                u1r = fma(ft[8 * k + 4], c, u1r);
+                u1i = fma(ft[8 * k + 5], c, u1i);
+                u1r = fma(-ft[8 * k + 7], sn, u1r);
+                u1i = fma(ft[8 * k + 6], sn, u1i);
+            }
+            U0r += (double)u0r;
+            U0i += (double)u0i;
+            U1r += (double)u1r;
+            U1i += (double)u1i;
+        }
+        const double im0 = hc * U0i + hs * U0r;
+        const double re0 = hc * U0r - hs * U0i;
+        const double im1 = hc * U1i + hs * U1r;
+        fx = fma((double)nx, im0, fx);
+        fy = fma((double)ny, im0, fy);
+        fz += im1;
+        ph += re0;
+    }
+    red[0][t] = fx;
+    red[1][t] = fy;
+    red[2][t] = fz;
+    red[3][t] = ph;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[e][t] += red[e][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double f = 2.0 * q[j] * (6.283185307179586476925286766559 * invL);
+        const double Fx = f * red[0][0], Fy = f * red[1][0], Fz = f * red[2][0];
+        if (F) {
+            F[j] = Fx;
+            F[N + j] = Fy;
+            F[2 * N + j] = Fz;
+        }
+        if (phi) phi[j] = 2.0 * red[3][0];
+        if (kick != 0.0) {
+            const double a = kick / m[j];
+            vel[j] += a * Fx;
+            vel[N + j] += a * Fy;
+            vel[2 * N + j] += a * Fz;
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const double *m,
                         double *vel, const T *ftab, const T *psi0, const Geom &g, double L,
                         int64_t N, double kick, double *F, double *phi)
 {
+    if (N <= force_small_max<T>()) {
+        hipLaunchKernelGGL(k_force_small<T>, dim3((unsigned)N), dim3(256), 0, s, pos, q, m, vel, ftab,
+                           psi0, g.n, g.R, g.nzp, 1.0 / L, N, kick, F, phi);
+        return hipGetLastError();
+    }
     const int64_t blocks = (N + 255) / 256;
     const int nzc = force_chunk(g.n, (int)sizeof(T));
     if (nzc == 8)

@@ -96,6 +96,23 @@ def test_deposit_and_force_match_oracle(references, name, prec):
     assert abs(d.interaction - 2 * ref.W) <= (1e-12 if prec == "fp64" else 1e-5) * abs(ref.W)
 
 
+@pytest.mark.parametrize("prec,N", [("fp32", 8192), ("fp32", 8193), ("fp64", 16384), ("fp64", 16385)])
+def test_force_either_side_of_the_small_count_kernel(prec, N):
+    """Up to 8192 (FP32) or 16384 (FP64) particles the force sum runs one
+    particle per block with the rows split over the threads; above, one
+    particle per lane.  Both sides of each switch against the oracle."""
+    sce = _gpu()
+    p = workloads.random_plasma(N=N, n_max=8, a=0.04, salt=N)
+    ref = oracle.fields(p.positions(), p.q, p.L, p.n_max, p.shape, p.a, p.eps0)
+    with sce.Context.from_particles(p, precision=prec) as c:
+        F = c.sce_force()
+        d, st = c.sce_diagnostics()
+    err = e_F(F, ref.F)
+    ew = abs(d.interaction - 2 * ref.W) / abs(2 * ref.W)  # sum_j q_j Phi_j = 2 W
+    print(f"N={N} {prec}: e_F={err:.3e} e_int={ew:.3e}")
+    assert err <= TOL[prec] and ew <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_random_plasma_full_size_sampled(prec):
     """N = 65536, n_max = 16: rho on sampled modes, F on sampled particles
