@@ -52,6 +52,7 @@ symmetries, reversibility and the h^2 energy error of the steps).
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import numpy as np
 import scipy.sparse as sp
@@ -149,9 +150,22 @@ def envelope(pos, L: float, w: float | None = None):
     x = np.atleast_2d(np.asarray(pos, dtype=np.float64))
     dk, w = _width(L, w)
     u = 0.5 * w * x
-    s = np.where(u == 0.0, 1.0, np.sin(u) / np.where(u == 0.0, 1.0, u))
-    # d/dx sinc^2(u) = 2 sinc(u) sinc'(u) du/dx, sinc'(u) = (cos u - sinc u) / u
-    ds = np.where(u == 0.0, 0.0, (np.cos(u) - s) / np.where(u == 0.0, 1.0, u))
+    # d/dx sinc^2(u) = 2 sinc(u) sinc'(u) du/dx, sinc'(u) = (cos u - sinc u) / u.
+    # For |u| < 0.1 that difference cancels; there both come from the series
+    # sinc(u) = sum_k (-u^2)^k / (2k+1)!, k <= 6.
+    small = np.abs(u) < 0.1
+    us = np.where(small, 1.0, u)
+    s = np.where(small, 0.0, np.sin(us) / us)
+    ds = np.where(small, 0.0, (np.cos(us) - np.sin(us) / us) / us)
+    s_ser = np.zeros_like(u)
+    ds_ser = np.zeros_like(u)
+    for k in range(7):
+        c = (-1.0) ** k / math.factorial(2 * k + 1)
+        s_ser += c * u ** (2 * k)
+        if k > 0:
+            ds_ser += c * 2 * k * u ** (2 * k - 1)
+    s = np.where(small, s_ser, s)
+    ds = np.where(small, ds_ser, ds)
     e = w / np.sqrt(TWO_PI) * s * s
     de = w / np.sqrt(TWO_PI) * 2.0 * s * ds * 0.5 * w
     E = np.prod(e, axis=0)
@@ -177,6 +191,20 @@ def deposit(pos, q, n: int, L: float, w: float | None = None, chunk: int = 2048)
     r = np.zeros((2 * n + 1) ** x.shape[0], dtype=np.complex128)
     for j0 in range(0, x.shape[1], chunk):
         r += basis(x[:, j0:j0 + chunk], n, L, w) @ q[j0:j0 + chunk]
+    return r
+
+
+def deposit_modes(pos, q, L: float, sig: np.ndarray, w: float | None = None,
+                  chunk: int = 65536) -> np.ndarray:
+    """r_sigma for the listed modes only (sig [K, dim]), same sum as ``deposit``."""
+    x = np.atleast_2d(np.asarray(pos, dtype=np.float64))
+    q = np.asarray(q, dtype=np.float64)
+    k = np.asarray(sig, dtype=np.float64) * (TWO_PI / L)
+    r = np.zeros(len(k), dtype=np.complex128)
+    for j0 in range(0, x.shape[1], chunk):
+        xs = x[:, j0:j0 + chunk]
+        E, _ = envelope(xs, L, w)
+        r += np.exp(1j * (k @ xs)) @ (q[j0:j0 + chunk] * E)
     return r
 
 

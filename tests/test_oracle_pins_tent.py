@@ -164,6 +164,17 @@ def test_basis_matches_defining_integral():
             assert abs(f[idx, j] - val) <= 1e-11 * max(1.0, abs(val)), (s, j)
 
 
+def test_deposit_on_listed_modes_matches_full_cube():
+    rng = np.random.default_rng(13)
+    x, q = _neutral(rng, 3, 50)
+    n, L = 3, 1.0
+    full = tf.deposit(x, q, n, L)
+    m = tf.modes(n, 3)
+    pick = rng.choice(len(m), 20, replace=False)
+    part = tf.deposit_modes(x, q, L, m[pick], chunk=7)
+    assert np.allclose(part, full[pick], rtol=1e-13, atol=1e-13 * np.max(np.abs(full)))
+
+
 def test_envelope_gradient_central_difference():
     rng = np.random.default_rng(5)
     x = rng.uniform(-0.8, 0.8, (3, 7))
