@@ -53,12 +53,14 @@ def parse():
                     help="requests of the serving workload (0 = skip the serving run)")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load as a fraction of the measured saturated capacity")
-    ap.add_argument("--study", default="", choices=["", "longrun", "dispersion", "h2", "twod"],
+    ap.add_argument("--study", default="", choices=["", "longrun", "dispersion", "h2", "twod", "tent"],
                     help="run one validation study instead of the throughput benchmark")
     ap.add_argument("--long-steps", type=int, default=100000,
                     help="steps of the long-run conservation study")
     ap.add_argument("--long-precisions", default="split_f16,fp32,fp64",
                     help="comma list of precisions of the long-run study")
+    ap.add_argument("--tent-precisions", default="split_f16,fp32,fp64",
+                    help="comma list of precisions of the tent-field study")
     ap.add_argument("--twod-steps", type=int, default=200000,
                     help="steps of each long run of the two-dimensional study")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -451,6 +453,40 @@ def study_twod(sce, steps):
     return out
 
 
+def study_tent(sce, steps, warmup, precisions):
+    """Finite-width (tent) field shapes at the size of the headline workload:
+    N = 1,048,576 point charges uniform in [-L/4, L/4]^3, n_max = 32 (the
+    274,625-mode cube, origin included, 137,313 stored), KDK, dt = 1e-3.  Per
+    precision: wall time per step and the deposit and force kernel times, next
+    to the periodic delta-field step of the cold lattice at the same N and
+    n_max; the difference is the tent solve, the envelope and the combine.
+    Energy and momentum change over the run (FP64 diagnostics)."""
+    import numpy as np
+    import workloads
+    pt = workloads.tent_plasma(N=1 << 20, n_max=32, dim=3)
+    pd = workloads.cold_lattice()
+    rows = []
+    for prec in precisions:
+        for field, p in (("tent", pt), ("delta", pd)):
+            r = time_path(sce, p, prec, steps, warmup)
+            rows.append({"field": field, "precision": prec,
+                         "ms_per_step": round(r["ms_per_step"], 4),
+                         "deposit_ms_avg": round(r["deposit_ms_avg"], 4),
+                         "force_ms_avg": round(r["force_ms_avg"], 4),
+                         "pairs_per_s": r["pairs_per_s"], "modes_stored": r["modes_half"]})
+            print(f"tent study {field} {prec} done", file=sys.stderr, flush=True)
+    cons = {}
+    with sce.Context.from_particles(pt, precision="split_f16") as c:
+        d0, _ = c.sce_diagnostics()
+        c.sce_step(pt.dt, 200)
+        d1, _ = c.sce_diagnostics()
+    cons = {"steps": 200, "E0": d0.total, "dE_rel": abs(d1.total - d0.total) / abs(d0.total),
+            "dP_rel": float(np.linalg.norm(d1.momentum - d0.momentum) / d0.momentum_abs_sum)}
+    return {"study": "tent", "rows": rows, "split_f16_conservation": cons,
+            "workload": "tent_plasma N=1048576 n_max=32 3-D in [-L/4, L/4]^3 (tent field, point particles) "
+                        "vs cold_lattice_128x128x64_n32 (delta field, Gaussian a = 0.01)"}
+
+
 def cpu_baseline(p, sample):
     import numpy as np
     import oracle
@@ -488,6 +524,8 @@ def main():
             r = study_dispersion(sce)
         elif a.study == "twod":
             r = study_twod(sce, a.twod_steps)
+        elif a.study == "tent":
+            r = study_tent(sce, a.steps, a.warmup, [x for x in a.tent_precisions.split(",") if x])
         else:
             r = study_h2(sce)
         print(json.dumps(r), flush=True)

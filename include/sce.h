@@ -80,6 +80,10 @@ typedef enum {
 
 typedef enum { SCE_SCHEME_KDK = 0, SCE_SCHEME_DKD = 1 } sce_scheme;
 
+/* Field shape Psi of the potential's modes (Section 3): delta functions (the
+ * periodic box above) or tents of half-width dk (sce_create_tent). */
+typedef enum { SCE_FIELD_DELTA = 0, SCE_FIELD_TENT = 1 } sce_field_kind;
+
 typedef struct sce_ctx_s *sce_ctx;
 
 /* Diagnostics at the current state (Section 6 reports energy and its kinetic,
@@ -88,8 +92,10 @@ typedef struct {
     int64_t step;              /* steps taken since the particles were set */
     double time;               /* sum of dt over those steps */
     double kinetic;            /* K = 1/2 sum m |v|^2 */
-    double field;              /* W = (1/(eps0 V)) sum_H |rho|^2/|k|^2 at the current positions */
-    double field_self;         /* (sum q^2/(eps0 V)) sum_H S^2/|k|^2: constant self-energy within W */
+    double field;              /* W = (1/(eps0 V)) sum_H |rho|^2/|k|^2 at the current positions
+                                  (tent fields: (eps0/2) phi^T K phi) */
+    double field_self;         /* (sum q^2/(eps0 V)) sum_H S^2/|k|^2: constant self-energy within W
+                                  (0 for tent fields, where it depends on the positions) */
     double interaction;        /* sum_j q_j Phi_j, Phi_j = 2 sum_H Re(psi e^{i k.x_j}); equals 2 W */
     double total;              /* K + W */
     double momentum[3];        /* sum m v */
@@ -126,6 +132,38 @@ sce_status sce_create_2d(double L, int32_t n_max, int32_t shape_kind, double sha
 /* Spatial dimension of the context (3, or 2 for sce_create_2d). */
 sce_status sce_dimension(sce_ctx ctx, int32_t *dim);
 
+/* Finite-width field shapes (Section 3, the potential's expansion and the
+ * k-squared matrix; Section 4, the discrete Euler-Lagrange equations), the
+ * variant the paper describes and then sets aside.  The potential is
+ * expanded over modes s in the full cube {-n_max..n_max}^D, s = 0 included,
+ * k_s = dk s, dk = 2 pi / L, each spread over k-space by a tent
+ * Psi(k - k_s) = prod_d max(0, 1 - |k_d - k_s,d| / dk); neighbouring tents
+ * overlap, so the potential's transform is piecewise linear.  The field
+ * lives on all of R^D: there is no periodic box and positions are never
+ * wrapped.  Particles are points (Lambda = delta), which gives the
+ * particle-mode integral the closed form f_s(x) = e^{i k_s.x} E(x),
+ * E(x) = prod_d (2 pi)^(-1/2) dk sinc^2(dk x_d / 2).  Then
+ *   deposit  rho_s = sum_j q_j E(x_j) e^{-i k_s.x_j}, the conjugate of the
+ *            paper's right-hand side sum_j q_j f_s(x_j);
+ *   solve    eps0 sum_s' K_{s s'} phi_s' = conj(rho_s),
+ *            K_{s s'} = int |k|^2 Psi(k - k_s) Psi(-k - k_s') dk, solved exactly
+ *            (eps0 = 1/(4 pi) gives the Gaussian-unit factor 4 pi);
+ *   force    F_j = -q_j sum_s phi_s grad f_s(x_j); Phi_j = sum_s phi_s f_s(x_j);
+ *   energy   W = (eps0/2) phi^T K phi = (1/2) sum_j q_j Phi_j.
+ * Translations are not a symmetry, so momentum is not conserved (a lone
+ * particle away from the origin feels a force); the steps are those of the
+ * periodic model without the wrap.  dim: 3, or 2 (line charges with the
+ * conventions of sce_create_2d: arrays [2][N], 2 ints per mode).  The stored
+ * modes are the origin followed by H in canonical order, |H| + 1 of them:
+ * sce_mode_count, sce_modes, sce_deposit, sce_psi (which returns phi) and the
+ * rho_abs of sce_diagnostics use that set.  Every precision and scheme is
+ * available.  Errors: SCE_EINVAL if L <= 0 or non-finite, n_max < 1 or
+ * n_max > 64, dim not 2 or 3, out == NULL. */
+sce_status sce_create_tent(double L, int32_t n_max, int32_t dim, sce_ctx *out);
+
+/* Field shape of the context: SCE_FIELD_DELTA or SCE_FIELD_TENT. */
+sce_status sce_field_shape(sce_ctx ctx, int32_t *field);
+
 /* eps0 > 0; precision: sce_precision; scheme: sce_scheme; hip_stream: a
  * hipStream_t on the context's device, or NULL for the context's own stream.
  * Invalidates cached fields.  SCE_EINVAL on bad values. */
@@ -133,7 +171,8 @@ sce_status sce_set_options(sce_ctx ctx, double eps0, int32_t precision, int32_t 
                            void *hip_stream);
 
 /* Copy N particles into the context.  x, v: [3][N]; q, m: [N] (m > 0).
- * Positions outside [0, L) are accepted and wrapped.  Resets the step counter
+ * Positions outside [0, L) are accepted and wrapped (kept as given in a
+ * tent-field context).  Resets the step counter
  * and the cached force.  SCE_EINVAL if N < 1 or a pointer is NULL. */
 sce_status sce_set_particles(sce_ctx ctx, int64_t N, const double *x, const double *v,
                              const double *q, const double *m, int32_t on_device);
@@ -141,7 +180,7 @@ sce_status sce_set_particles(sce_ctx ctx, int64_t N, const double *x, const doub
 /* Copy positions and velocities out ([3][N] each; either may be NULL). */
 sce_status sce_get_particles(sce_ctx ctx, double *x, double *v, int32_t on_device);
 
-/* Number of stored half-space modes |H|. */
+/* Number of stored half-space modes |H| (|H| + 1 with tent fields). */
 sce_status sce_mode_count(sce_ctx ctx, int64_t *n_half);
 
 /* The stored modes in canonical order: nxyz[3*i + d] = n_d of mode i (2 ints

@@ -486,12 +486,18 @@ hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, co
 // ------------------------------------------------------------------ force
 // One particle per lane.  Rows are visited in the same order by every lane,
 // so the force table entries of a row are wave-uniform (scalar loads); the
-// lane's cos/sin(n_z tz) for a chunk of NZC values stay in registers.
-template <typename T, int NZC>
+// lane's cos/sin(n_z tz) for a chunk of NZC values stay in registers.  PLANE:
+// a two-dimensional context (rows of n_x = 0 only).  The number of n_x lines
+// is a compile-time choice on purpose: the row loop is bound by the latency
+// of the table's scalar loads, which the compiler hides by double-buffering
+// them in SGPRs, and one more live scalar (a runtime line count) leaves no
+// room for the second buffer (measured: FP64 force 37 -> 55 ms at 2^20
+// particles, n_max = 32).
+template <typename T, int NZC, bool PLANE>
 __global__ void __launch_bounds__(256)
 k_force(const double *__restrict__ pos, const double *__restrict__ q,
         const double *__restrict__ m, double *__restrict__ vel, const T *__restrict__ ftab,
-        const T *__restrict__ psi0, int n, int lines, int nzp, double invL, int64_t N,
+        const T *__restrict__ psi0, int n, int nzp, double invL, int64_t N,
         double kick, double *__restrict__ F, double *__restrict__ phi)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -523,7 +529,7 @@ k_force(const double *__restrict__ pos, const double *__restrict__ q,
             }
         }
         int r = 0;
-        for (int nx = 0; nx < lines; ++nx) {
+        for (int nx = 0; nx <= (PLANE ? 0 : n); ++nx) {
             const int ny0 = nx == 0 ? 0 : -n;
             double hc, hs;
             cis_turns(frac_lin(nx, tx, ny0, ty), hc, hs);
@@ -678,6 +684,17 @@ k_force_small(const double *__restrict__ pos, const double *__restrict__ q,
     }
 }
 
+template <typename T, int NZC, bool PLANE>
+hipError_t launch_force_chunk(hipStream_t s, const double *pos, const double *q, const double *m,
+                              double *vel, const T *ftab, const T *psi0, const Geom &g, double L,
+                              int64_t N, double kick, double *F, double *phi)
+{
+    const int64_t blocks = (N + 255) / 256;
+    hipLaunchKernelGGL((k_force<T, NZC, PLANE>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
+                       vel, ftab, psi0, g.n, g.nzp, 1.0 / L, N, kick, F, phi);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const double *m,
                         double *vel, const T *ftab, const T *psi0, const Geom &g, double L,
@@ -688,18 +705,17 @@ hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const
                            psi0, g.n, g.R, g.nzp, 1.0 / L, N, kick, F, phi);
         return hipGetLastError();
     }
-    const int64_t blocks = (N + 255) / 256;
     const int nzc = force_chunk(g.n, (int)sizeof(T));
-    if (nzc == 8)
-        hipLaunchKernelGGL((k_force<T, 8>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
-                           vel, ftab, psi0, g.n, g.lines, g.nzp, 1.0 / L, N, kick, F, phi);
-    else if (nzc == 16)
-        hipLaunchKernelGGL((k_force<T, 16>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
-                           vel, ftab, psi0, g.n, g.lines, g.nzp, 1.0 / L, N, kick, F, phi);
-    else
-        hipLaunchKernelGGL((k_force<T, 32>), dim3((unsigned)blocks), dim3(256), 0, s, pos, q, m,
-                           vel, ftab, psi0, g.n, g.lines, g.nzp, 1.0 / L, N, kick, F, phi);
-    return hipGetLastError();
+    if (g.lines == 1) {
+        if (nzc == 8) return launch_force_chunk<T, 8, true>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi);
+        if (nzc == 16 || sizeof(T) == 8) return launch_force_chunk<T, 16, true>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi);
+        if constexpr (sizeof(T) == 4) return launch_force_chunk<T, 32, true>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi);
+    } else {
+        if (nzc == 8) return launch_force_chunk<T, 8, false>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi);
+        if (nzc == 16 || sizeof(T) == 8) return launch_force_chunk<T, 16, false>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi);
+        if constexpr (sizeof(T) == 4) return launch_force_chunk<T, 32, false>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi);
+    }
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------ drift / kick
@@ -712,7 +728,8 @@ __device__ inline double wrap_box(double x, double L, double invL)
 
 __global__ void __launch_bounds__(256)
 k_kick_drift(double *__restrict__ pos, double *__restrict__ vel, const double *__restrict__ F,
-             const double *__restrict__ m, int64_t N, double L, double invL, double a, double b)
+             const double *__restrict__ m, int64_t N, double L, double invL, double a, double b,
+             int wrap)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= N) return;
@@ -723,16 +740,19 @@ k_kick_drift(double *__restrict__ pos, double *__restrict__ vel, const double *_
             v += am * F[d * N + j];
             vel[d * N + j] = v;
         }
-        if (b != 0.0) pos[d * N + j] = wrap_box(pos[d * N + j] + b * v, L, invL);
+        if (b != 0.0) {
+            const double x = pos[d * N + j] + b * v;
+            pos[d * N + j] = wrap ? wrap_box(x, L, invL) : x;
+        }
     }
 }
 
 hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *F,
-                             const double *m, int64_t N, double L, double a, double b)
+                             const double *m, int64_t N, double L, double a, double b, bool wrap)
 {
     const int64_t blocks = (N + 255) / 256;
     hipLaunchKernelGGL(k_kick_drift, dim3((unsigned)blocks), dim3(256), 0, s, pos, vel, F, m, N,
-                       L, 1.0 / L, a, b);
+                       L, 1.0 / L, a, b, wrap ? 1 : 0);
     return hipGetLastError();
 }
 

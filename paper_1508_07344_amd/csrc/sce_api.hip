@@ -35,6 +35,9 @@ struct sce_ctx_s {
 
     double L = 1.0, width = 0.0, eps0 = 1.0;
     int dim = 3;  // 2: line charges, stored with x = 0 and (y, z) = their (x, y)
+    // SCE_FIELD_TENT: tent field shapes on all of R^D, point particles, the
+    // origin mode kept, no wrap (see sce_create_tent)
+    int field = SCE_FIELD_DELTA;
     int kind = SCE_SHAPE_GAUSSIAN;
     int prec = SCE_PREC_FP64;
     int scheme = SCE_SCHEME_KDK;
@@ -63,6 +66,12 @@ struct sce_ctx_s {
     double *dscratch = nullptr;
     size_t dscratch_bytes = 0;
     double *dout = nullptr;
+    // tent field shapes: weighted charges, envelope [4][N], force-kernel F and
+    // P before the envelope, the mode cube (two buffers), the 1-D eigenbases
+    double *qw = nullptr, *env = nullptr, *Fk = nullptr, *Pk = nullptr;
+    double2 *cubeX = nullptr, *cubeY = nullptr;
+    double *Vf = nullptr, *Vb = nullptr, *lam = nullptr;
+    double env_max = 1.0;  // E(0), the largest envelope value
 
     bool fields_valid = false;  // rho/psi/W/ftab correspond to the current positions
     bool force_valid = false;   // F corresponds to the current positions
@@ -166,11 +175,19 @@ hipError_t dev_alloc(T *&p, size_t bytes)
     return e;
 }
 
+// Stored modes exported through the ABI: H, preceded by the origin in a
+// tent-field context; the origin sits just before H in the padded layout.
+int64_t export_first(sce_ctx c) { return c->field == SCE_FIELD_TENT ? c->g.n : c->g.n1; }
+int64_t export_count(sce_ctx c) { return c->field == SCE_FIELD_TENT ? c->g.H + 1 : c->g.H; }
+
 // Box volume V = L^3, or the area A = L^2 of a two-dimensional context.
 double box_measure(sce_ctx c) { return c->dim == 2 ? c->L * c->L : c->L * c->L * c->L; }
 
 // Green tables for (row, |n_z|): S, G = S / (eps0 k^2 V), K = 1 / (eps0 k^2 V)
 // (V = A in two dimensions; there k_x = 0 for every stored mode).
+// Tent field shapes: S = 1 for every stored mode, the origin included, and
+// G = K = 0: the reduce/solve kernel then leaves rho only, and the tent solve
+// writes psi, the force table and the energy partials.
 sce_status build_tables(sce_ctx c)
 {
     const Geom &g = c->g;
@@ -178,7 +195,13 @@ sce_status build_tables(sce_ctx c)
     std::vector<double> S(cnt), G(cnt), K(cnt);
     const double f = kTwoPi / c->L, V = box_measure(c);
     double self = 0.0;
-    for (int r = 0; r < g.R; ++r) {
+    for (int r = 0; r < g.R && c->field == SCE_FIELD_TENT; ++r)
+        for (int nz = 0; nz <= g.n; ++nz) {
+            const size_t i = (size_t)r * g.n1 + nz;
+            S[i] = 1.0;
+            G[i] = K[i] = 0.0;
+        }
+    for (int r = 0; r < g.R && c->field != SCE_FIELD_TENT; ++r) {
         int nx, ny;
         sce::row_nxny(r, g.n, nx, ny);
         for (int nz = 0; nz <= g.n; ++nz) {
@@ -207,6 +230,133 @@ sce_status build_tables(sce_ctx c)
     HIPCHK(c, hipMemcpy(c->Stab, S.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->Gtab, G.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->Ktab, K.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+    return SCE_OK;
+}
+
+// Tent tables.  The 1-D Gram integrals of tents of half-width dk centred at
+// a dk, a = -n..n, have closed forms (c = a dk):
+//   B(a,a) = 2 dk / 3,                  B(a,a+1) = dk / 6,
+//   A(a,a) = (2/3) c^2 dk + dk^3 / 15,  A(a,a+1) = dk (c^2 / 6 + c dk / 6 + dk^2 / 20),
+// zero beyond neighbours (B: int T T, A: int k^2 T T).  The generalised
+// eigenproblem A v = lambda B v with V^T B V = I is solved by the Cholesky
+// factor B = C C^T, cyclic Jacobi rotations on S = C^-1 A C^-T = W diag(lambda)
+// W^T, and V = C^-T W; the tensor products of V then diagonalise the D-D
+// matrix sum_d A (x) B (x) B (permuted).
+sce_status tent_tables(sce_ctx c)
+{
+    const int n = c->g.n, M = c->g.M;
+    const double dk = kTwoPi / c->L;
+    std::vector<double> A((size_t)M * M, 0.0), B((size_t)M * M, 0.0);
+    for (int i = 0; i < M; ++i) {
+        const double ca = (i - n) * dk;
+        B[i * M + i] = 2.0 * dk / 3.0;
+        A[i * M + i] = 2.0 / 3.0 * ca * ca * dk + dk * dk * dk / 15.0;
+        if (i + 1 < M) {
+            B[i * M + i + 1] = B[(i + 1) * M + i] = dk / 6.0;
+            A[i * M + i + 1] = A[(i + 1) * M + i] = dk * (ca * ca / 6.0 + ca * dk / 6.0 + dk * dk / 20.0);
+        }
+    }
+    std::vector<double> C((size_t)M * M, 0.0);
+    for (int j = 0; j < M; ++j) {
+        double d = B[j * M + j];
+        for (int k = 0; k < j; ++k) d -= C[j * M + k] * C[j * M + k];
+        if (!(d > 0.0)) return fail(c, SCE_EDEVICE, "tent Gram matrix not positive definite");
+        C[j * M + j] = std::sqrt(d);
+        for (int i = j + 1; i < M; ++i) {
+            double s = B[i * M + j];
+            for (int k = 0; k < j; ++k) s -= C[i * M + k] * C[j * M + k];
+            C[i * M + j] = s / C[j * M + j];
+        }
+    }
+    // Y = C^-1 A, then S = C^-1 Y^T (= C^-1 A C^-T), symmetrised
+    std::vector<double> Y((size_t)M * M), S((size_t)M * M), W((size_t)M * M, 0.0);
+    for (int col = 0; col < M; ++col)
+        for (int i = 0; i < M; ++i) {
+            double s = A[i * M + col];
+            for (int k = 0; k < i; ++k) s -= C[i * M + k] * Y[k * M + col];
+            Y[i * M + col] = s / C[i * M + i];
+        }
+    for (int col = 0; col < M; ++col)
+        for (int i = 0; i < M; ++i) {
+            double s = Y[col * M + i];
+            for (int k = 0; k < i; ++k) s -= C[i * M + k] * S[k * M + col];
+            S[i * M + col] = s / C[i * M + i];
+        }
+    for (int i = 0; i < M; ++i)
+        for (int j = i + 1; j < M; ++j) S[i * M + j] = S[j * M + i] = 0.5 * (S[i * M + j] + S[j * M + i]);
+    for (int i = 0; i < M; ++i) W[i * M + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int p = 0; p < M; ++p) {
+            dia += S[p * M + p] * S[p * M + p];
+            for (int q = p + 1; q < M; ++q) off += S[p * M + q] * S[p * M + q];
+        }
+        if (off <= 1e-32 * dia) break;
+        for (int p = 0; p < M; ++p)
+            for (int q = p + 1; q < M; ++q) {
+                const double apq = S[p * M + q];
+                if (apq == 0.0) continue;
+                const double th = (S[q * M + q] - S[p * M + p]) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < M; ++k) {
+                    const double a = S[k * M + p], b = S[k * M + q];
+                    S[k * M + p] = cs * a - sn * b;
+                    S[k * M + q] = sn * a + cs * b;
+                }
+                for (int k = 0; k < M; ++k) {
+                    const double a = S[p * M + k], b = S[q * M + k];
+                    S[p * M + k] = cs * a - sn * b;
+                    S[q * M + k] = sn * a + cs * b;
+                }
+                for (int k = 0; k < M; ++k) {
+                    const double a = W[k * M + p], b = W[k * M + q];
+                    W[k * M + p] = cs * a - sn * b;
+                    W[k * M + q] = sn * a + cs * b;
+                }
+            }
+    }
+    std::vector<double> V((size_t)M * M), Vb((size_t)M * M), lam(M);
+    for (int i = 0; i < M; ++i) lam[i] = S[i * M + i];
+    for (int col = 0; col < M; ++col)
+        for (int i = M - 1; i >= 0; --i) {
+            double s = W[i * M + col];
+            for (int k = i + 1; k < M; ++k) s -= C[k * M + i] * V[k * M + col];
+            V[i * M + col] = s / C[i * M + i];
+        }
+    // check V^T B V = I and V^T A V = diag(lambda)
+    double eb = 0.0, ea = 0.0, lmax = 0.0;
+    for (int i = 0; i < M; ++i) lmax = std::fmax(lmax, std::fabs(lam[i]));
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) {
+            double sb = 0.0, sa = 0.0;
+            for (int k = 0; k < M; ++k) {
+                double bk = 0.0, ak = 0.0;
+                for (int l = std::max(0, k - 1); l <= std::min(M - 1, k + 1); ++l) {
+                    bk += B[k * M + l] * V[l * M + j];
+                    ak += A[k * M + l] * V[l * M + j];
+                }
+                sb += V[k * M + i] * bk;
+                sa += V[k * M + i] * ak;
+            }
+            eb = std::fmax(eb, std::fabs(sb - (i == j ? 1.0 : 0.0)));
+            ea = std::fmax(ea, std::fabs(sa - (i == j ? lam[i] : 0.0)));
+        }
+    if (!(eb <= 1e-10 && ea <= 1e-10 * lmax))
+        return fail(c, SCE_EDEVICE, "tent eigenbasis check failed");
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) Vb[j * M + i] = V[i * M + j];
+    c->env_max = 1.0;
+    for (int d = 0; d < c->dim; ++d) c->env_max *= dk / std::sqrt(kTwoPi);
+    const size_t cube = (size_t)(c->dim == 2 ? 1 : M) * M * M;
+    HIPCHK(c, dev_alloc(c->Vf, (size_t)M * M * sizeof(double)));
+    HIPCHK(c, dev_alloc(c->Vb, (size_t)M * M * sizeof(double)));
+    HIPCHK(c, dev_alloc(c->lam, (size_t)M * sizeof(double)));
+    HIPCHK(c, dev_alloc(c->cubeX, cube * sizeof(double2)));
+    HIPCHK(c, dev_alloc(c->cubeY, cube * sizeof(double2)));
+    HIPCHK(c, hipMemcpy(c->Vf, V.data(), (size_t)M * M * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->Vb, Vb.data(), (size_t)M * M * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->lam, lam.data(), (size_t)M * sizeof(double), hipMemcpyHostToDevice));
     return SCE_OK;
 }
 
@@ -240,6 +390,16 @@ sce_status ensure_particle_buffers(sce_ctx c, int64_t N)
     free_devp(c->m);
     free_devp(c->F);
     free_devp(c->phi);
+    free_devp(c->qw);
+    free_devp(c->env);
+    free_devp(c->Fk);
+    free_devp(c->Pk);
+    if (c->field == SCE_FIELD_TENT) {
+        HIPCHK(c, dev_alloc(c->qw, N * sizeof(double)));
+        HIPCHK(c, dev_alloc(c->env, 4 * N * sizeof(double)));
+        HIPCHK(c, dev_alloc(c->Fk, 3 * N * sizeof(double)));
+        HIPCHK(c, dev_alloc(c->Pk, N * sizeof(double)));
+    }
     HIPCHK(c, dev_alloc(c->pos, 3 * N * sizeof(double)));
     HIPCHK(c, dev_alloc(c->vel, 3 * N * sizeof(double)));
     HIPCHK(c, dev_alloc(c->q, N * sizeof(double)));
@@ -288,6 +448,8 @@ sce_status run_deposit(sce_ctx c)
     c->part = (double *)pp;
     c->part_bytes = pb;
     if (st) return st;
+    const bool tent = c->field == SCE_FIELD_TENT;
+    if (tent) HIPCHK(c, sce::launch_tent_prep(c->stream, c->pos, c->q, c->N, c->dim, c->L, c->qw, c->env));
     HIPCHK(c, sce::launch_phase_table<T>(c->stream, c->pos, c->N, g, c->L, (double2 *)c->tabxy,
                                          (T *)c->tab));
     EventPair ep{nullptr, nullptr};
@@ -296,8 +458,8 @@ sce_status run_deposit(sce_ctx c)
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
-    HIPCHK(c, sce::launch_deposit<T>(c->stream, (const double2 *)c->tabxy, (const T *)c->tab, c->q,
-                                     c->N, g, pl, c->part));
+    HIPCHK(c, sce::launch_deposit<T>(c->stream, (const double2 *)c->tabxy, (const T *)c->tab,
+                                     tent ? c->qw : c->q, c->N, g, pl, c->part));
     if (c->timing && ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_dep.push_back(ep);
@@ -305,6 +467,10 @@ sce_status run_deposit(sce_ctx c)
     HIPCHK(c, sce::launch_reduce_solve<T>(c->stream, c->part, pl.splits, g, c->Stab, c->Gtab,
                                           c->Ktab, c->rho, c->psi, (T *)c->ftab, (T *)c->psi0,
                                           c->wpart, &c->wblocks));
+    if (tent)
+        HIPCHK(c, sce::launch_tent_solve<T>(c->stream, c->rho, g, c->dim, c->Vf, c->Vb, c->lam,
+                                            c->eps0, c->cubeX, c->cubeY, c->psi, (T *)c->ftab,
+                                            (T *)c->psi0, c->wpart, &c->wblocks));
     c->fields_valid = true;
     return SCE_OK;
 }
@@ -318,12 +484,17 @@ sce_status run_force(sce_ctx c, double kick)
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
+    const bool tent = c->field == SCE_FIELD_TENT;
     HIPCHK(c, sce::launch_force<T>(c->stream, c->pos, c->q, c->m, c->vel, (const T *)c->ftab,
-                                   (const T *)c->psi0, c->g, c->L, c->N, kick, c->F, c->phi));
+                                   (const T *)c->psi0, c->g, c->L, c->N, tent ? 0.0 : kick,
+                                   tent ? c->Fk : c->F, tent ? c->Pk : c->phi));
     if (c->timing && ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_frc.push_back(ep);
     }
+    if (tent)
+        HIPCHK(c, sce::launch_tent_combine(c->stream, c->env, c->q, c->m, c->Fk, c->Pk, c->N, kick,
+                                           c->vel, c->F, c->phi));
     c->force_valid = true;
     c->phi_valid = true;
     return SCE_OK;
@@ -349,8 +520,10 @@ sce_status run_deposit_split(sce_ctx c)
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
-    HIPCHK(c, sce::launch_deposit_mfma(c->stream, c->pos, c->q, c->N, g, c->L, pl, c->qscale,
-                                       (float *)c->turns, c->part));
+    const bool tent = c->field == SCE_FIELD_TENT;
+    if (tent) HIPCHK(c, sce::launch_tent_prep(c->stream, c->pos, c->q, c->N, c->dim, c->L, c->qw, c->env));
+    HIPCHK(c, sce::launch_deposit_mfma(c->stream, c->pos, tent ? c->qw : c->q, c->N, g, c->L, pl,
+                                       c->qscale, (float *)c->turns, c->part));
     if (c->timing && ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_dep.push_back(ep);
@@ -358,6 +531,11 @@ sce_status run_deposit_split(sce_ctx c)
     HIPCHK(c, sce::launch_reduce_solve<float>(c->stream, c->part, pl.splits, g, c->Stab, c->Gtab,
                                               c->Ktab, c->rho, c->psi, (float *)c->ftab,
                                               (float *)c->psi0, c->wpart, &c->wblocks));
+    if (tent)
+        HIPCHK(c, sce::launch_tent_solve<float>(c->stream, c->rho, g, c->dim, c->Vf, c->Vb, c->lam,
+                                                c->eps0, c->cubeX, c->cubeY, c->psi,
+                                                (float *)c->ftab, (float *)c->psi0, c->wpart,
+                                                &c->wblocks));
     HIPCHK(c, sce::launch_force_pack(c->stream, (const float *)c->ftab, (const float *)c->psi0, g,
                                      reinterpret_cast<float4 *>(c->wscr), (_Float16 *)c->wf));
     c->fields_valid = true;
@@ -372,15 +550,20 @@ sce_status run_force_split(sce_ctx c, double kick, bool want_phi)
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
+    const bool tent = c->field == SCE_FIELD_TENT;
     HIPCHK(c, sce::launch_force_mfma(c->stream, c->pos, c->q, c->m, c->vel, (const _Float16 *)c->wf,
                                      reinterpret_cast<const float4 *>(c->wscr), c->g, c->L, c->N,
-                                     kick, c->F, want_phi ? c->phi : nullptr));
+                                     tent ? 0.0 : kick, tent ? c->Fk : c->F,
+                                     tent ? c->Pk : (want_phi ? c->phi : nullptr)));
     if (c->timing && ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_frc.push_back(ep);
     }
+    if (tent)
+        HIPCHK(c, sce::launch_tent_combine(c->stream, c->env, c->q, c->m, c->Fk, c->Pk, c->N, kick,
+                                           c->vel, c->F, c->phi));
     c->force_valid = true;
-    c->phi_valid = want_phi;
+    c->phi_valid = want_phi || tent;
     return SCE_OK;
 }
 
@@ -457,7 +640,7 @@ const char *sce_last_error(sce_ctx c) { return c ? c->err.c_str() : "null contex
 
 namespace {
 sce_status create_ctx(double L, int32_t n_max, int32_t shape_kind, double shape_width, int dim,
-                      sce_ctx *out)
+                      int field, sce_ctx *out)
 {
     if (!out) return SCE_EINVAL;
     *out = nullptr;
@@ -471,6 +654,7 @@ sce_status create_ctx(double L, int32_t n_max, int32_t shape_kind, double shape_
     c->kind = shape_kind;
     c->width = shape_width;
     c->dim = dim;
+    c->field = field;
     c->g = make_geom(n_max, dim);
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
@@ -480,6 +664,7 @@ sce_status create_ctx(double L, int32_t n_max, int32_t shape_kind, double shape_
     }
     c->own_stream = true;
     sce_status st = build_tables(c);
+    if (!st && field == SCE_FIELD_TENT) st = tent_tables(c);
     if (!st) {
         const Geom &g = c->g;
         if (dev_alloc(c->rho, g.P * sizeof(double2)) != hipSuccess ||
@@ -502,12 +687,28 @@ extern "C" {
 
 sce_status sce_create(double L, int32_t n_max, int32_t shape_kind, double shape_width, sce_ctx *out)
 {
-    return create_ctx(L, n_max, shape_kind, shape_width, 3, out);
+    return create_ctx(L, n_max, shape_kind, shape_width, 3, SCE_FIELD_DELTA, out);
 }
 
 sce_status sce_create_2d(double L, int32_t n_max, int32_t shape_kind, double shape_width, sce_ctx *out)
 {
-    return create_ctx(L, n_max, shape_kind, shape_width, 2, out);
+    return create_ctx(L, n_max, shape_kind, shape_width, 2, SCE_FIELD_DELTA, out);
+}
+
+sce_status sce_create_tent(double L, int32_t n_max, int32_t dim, sce_ctx *out)
+{
+    if (dim != 2 && dim != 3) {
+        if (out) *out = nullptr;
+        return SCE_EINVAL;
+    }
+    return create_ctx(L, n_max, SCE_SHAPE_DELTA, 0.0, dim, SCE_FIELD_TENT, out);
+}
+
+sce_status sce_field_shape(sce_ctx c, int32_t *field)
+{
+    if (!c || !field) return SCE_EINVAL;
+    *field = c->field;
+    return SCE_OK;
 }
 
 sce_status sce_dimension(sce_ctx c, int32_t *dim)
@@ -573,7 +774,7 @@ sce_status sce_set_particles(sce_ctx c, int64_t N, const double *x, const double
     }
     if ((st = copy_in(c, c->q, q, N * sizeof(double), on_device))) return st;
     if ((st = copy_in(c, c->m, m, N * sizeof(double), on_device))) return st;
-    HIPCHK(c, sce::launch_wrap(c->stream, c->pos, N, c->L));
+    if (c->field != SCE_FIELD_TENT) HIPCHK(c, sce::launch_wrap(c->stream, c->pos, N, c->L));
     // sum q^2 for the self-energy (host copy of q)
     std::vector<double> hq(N);
     HIPCHK(c, hipMemcpyAsync(hq.data(), c->q, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -585,6 +786,7 @@ sce_status sce_set_particles(sce_ctx c, int64_t N, const double *x, const double
     }
     c->q2sum = s;
     c->qscale = qmax > 0.0 ? qmax : 1.0;
+    if (c->field == SCE_FIELD_TENT) c->qscale *= c->env_max;  // the deposit takes q E, E <= E(0)
     c->gen++;  // N, qscale and the particle buffers are captured by a step graph
     c->step = 0;
     c->time = 0.0;
@@ -607,7 +809,7 @@ sce_status sce_get_particles(sce_ctx c, double *x, double *v, int32_t on_device)
 sce_status sce_mode_count(sce_ctx c, int64_t *n_half)
 {
     if (!c || !n_half) return SCE_EINVAL;
-    *n_half = c->g.H;
+    *n_half = export_count(c);
     return SCE_OK;
 }
 
@@ -620,7 +822,8 @@ sce_status sce_modes(sce_ctx c, int32_t *nxyz)
         int nx, ny;
         sce::row_nxny(r, g.n, nx, ny);
         for (int nz = -g.n; nz <= g.n; ++nz) {
-            if (!sce::in_half(nx, ny, nz)) continue;
+            const bool origin = nx == 0 && ny == 0 && nz == 0 && c->field == SCE_FIELD_TENT;
+            if (!sce::in_half(nx, ny, nz) && !origin) continue;
             if (c->dim == 2) {
                 nxyz[2 * i] = ny;
                 nxyz[2 * i + 1] = nz;
@@ -632,7 +835,7 @@ sce_status sce_modes(sce_ctx c, int32_t *nxyz)
             ++i;
         }
     }
-    return i == g.H ? SCE_OK : fail(c, SCE_EDEVICE, "mode count mismatch");
+    return i == export_count(c) ? SCE_OK : fail(c, SCE_EDEVICE, "mode count mismatch");
 }
 
 sce_status sce_deposit(sce_ctx c, double *rho, int32_t on_device)
@@ -641,7 +844,9 @@ sce_status sce_deposit(sce_ctx c, double *rho, int32_t on_device)
     if (st) return st;
     if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
     if ((st = deposit(c))) return st;
-    if (rho) return copy_out(c, rho, (const double *)(c->rho + c->g.n1), c->g.H * sizeof(double2), on_device);
+    if (rho)
+        return copy_out(c, rho, (const double *)(c->rho + export_first(c)),
+                        export_count(c) * sizeof(double2), on_device);
     return SCE_OK;
 }
 
@@ -651,7 +856,8 @@ sce_status sce_psi(sce_ctx c, double *psi, int32_t on_device)
     if (st) return st;
     if (!c->fields_valid) return fail(c, SCE_ESTATE, "no current deposit");
     if (!psi) return fail(c, SCE_EINVAL, "NULL psi");
-    return copy_out(c, psi, (const double *)(c->psi + c->g.n1), c->g.H * sizeof(double2), on_device);
+    return copy_out(c, psi, (const double *)(c->psi + export_first(c)),
+                    export_count(c) * sizeof(double2), on_device);
 }
 
 sce_status sce_force(sce_ctx c, double *F, int32_t on_device)
@@ -674,18 +880,19 @@ namespace {
 sce_status step_once(sce_ctx c, double dt)
 {
     sce_status st;
+    const bool wrap = c->field != SCE_FIELD_TENT;
     if (c->scheme == SCE_SCHEME_KDK) {
         if (!c->force_valid && (st = pass(c, 0.0))) return st;
         HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
-                                         0.5 * dt, dt));
+                                         0.5 * dt, dt, wrap));
         c->fields_valid = c->force_valid = false;
         if ((st = pass(c, 0.5 * dt))) return st;
     } else {
         HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
-                                         0.0, 0.5 * dt));
+                                         0.0, 0.5 * dt, wrap));
         if ((st = pass(c, dt))) return st;
         HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
-                                         0.0, 0.5 * dt));
+                                         0.0, 0.5 * dt, wrap));
         c->fields_valid = c->force_valid = false;
     }
     c->step += 1;
@@ -820,14 +1027,15 @@ sce_status sce_diagnostics(sce_ctx c, sce_diag *out, double *rho_abs)
     out->interaction = h[5];
     out->field = h[6];
     out->rho_abs_max = h[7];
-    out->field_self = c->q2sum / (c->eps0 * box_measure(c)) * c->self_sum;
+    out->field_self = c->field == SCE_FIELD_TENT ? 0.0 : c->q2sum / (c->eps0 * box_measure(c)) * c->self_sum;
     out->total = out->kinetic + out->field;
     if (rho_abs) {
-        std::vector<double2> r(c->g.H);
-        HIPCHK(c, hipMemcpyAsync(r.data(), c->rho + c->g.n1, c->g.H * sizeof(double2),
+        const int64_t cnt = export_count(c);
+        std::vector<double2> r(cnt);
+        HIPCHK(c, hipMemcpyAsync(r.data(), c->rho + export_first(c), cnt * sizeof(double2),
                                  hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        for (int64_t i = 0; i < c->g.H; ++i) rho_abs[i] = std::hypot(r[i].x, r[i].y);
+        for (int64_t i = 0; i < cnt; ++i) rho_abs[i] = std::hypot(r[i].x, r[i].y);
     }
     if (!std::isfinite(out->total)) return fail(c, SCE_EUNSTABLE, "non-finite energy");
     return SCE_OK;
@@ -843,7 +1051,7 @@ struct StateHeader {
     int32_t n_max;
     int32_t has_force;
     int32_t dim;
-    int32_t reserved;
+    int32_t field;
 };
 const uint64_t kMagic = 0x32454353484b5053ull;  // "SPKHSCE2"
 }  // namespace
@@ -860,7 +1068,8 @@ sce_status sce_get_state(sce_ctx c, void *buf, size_t *bytes)
         return SCE_OK;
     }
     if (*bytes < need) return fail(c, SCE_EINVAL, "buffer too small");
-    StateHeader hd{kMagic, c->N, c->step, c->time, c->L, c->g.n, c->force_valid ? 1 : 0, c->dim, 0};
+    StateHeader hd{kMagic, c->N, c->step, c->time, c->L, c->g.n, c->force_valid ? 1 : 0, c->dim,
+                   c->field};
     std::memcpy(buf, &hd, sizeof(hd));
     double *d = (double *)((char *)buf + sizeof(hd));
     const size_t n3 = 3 * c->N * sizeof(double), n1 = c->N * sizeof(double);
@@ -882,6 +1091,7 @@ sce_status sce_set_state(sce_ctx c, const void *buf, size_t bytes)
     StateHeader hd;
     std::memcpy(&hd, buf, sizeof(hd));
     if (hd.magic != kMagic || hd.N < 1 || hd.L != c->L || hd.n_max != c->g.n || hd.dim != c->dim ||
+        hd.field != c->field ||
         bytes < sizeof(hd) + (size_t)hd.N * 11 * sizeof(double))
         return fail(c, SCE_EINVAL, "checkpoint does not match this context");
     const double *d = (const double *)((const char *)buf + sizeof(hd));
@@ -974,6 +1184,15 @@ void sce_destroy(sce_ctx c)
     free_devp(c->wpart);
     free_devp(c->dscratch);
     free_devp(c->dout);
+    free_devp(c->qw);
+    free_devp(c->env);
+    free_devp(c->Fk);
+    free_devp(c->Pk);
+    free_devp(c->cubeX);
+    free_devp(c->cubeY);
+    free_devp(c->Vf);
+    free_devp(c->Vb);
+    free_devp(c->lam);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

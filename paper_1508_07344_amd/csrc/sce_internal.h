@@ -127,9 +127,9 @@ hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, 
                              double *vel, const _Float16 *wf, const float4 *rinfo, const Geom &g,
                              double L, int64_t N, double kick, double *F, double *phi);
 
-// v += a F/m (if a != 0); x = wrap(x + b v) (if b != 0).
+// v += a F/m (if a != 0); x = x + b v (if b != 0), wrapped into [0, L) when wrap.
 hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *F,
-                             const double *m, int64_t N, double L, double a, double b);
+                             const double *m, int64_t N, double L, double a, double b, bool wrap);
 
 // Wrap positions into [0, L).
 hipError_t launch_wrap(hipStream_t s, double *pos, int64_t N, double L);
@@ -140,5 +140,24 @@ hipError_t launch_wrap(hipStream_t s, double *pos, int64_t N, double L);
 hipError_t launch_diag(hipStream_t s, const double *vel, const double *q, const double *m,
                        const double *phi, int64_t N, const double *wpart, int wblocks,
                        double eps0V, double *scratch, double *out);
+
+// ---- finite-width tent field shapes, point particles (kernels_tent.hip)
+// Envelope E(x), its gradient (env [4][N]: E, dE/dx, dE/dy, dE/dz) and the
+// weighted charges qw = q E; dim 2 spans only the stored y and z.
+hipError_t launch_tent_prep(hipStream_t s, const double *pos, const double *q, int64_t N, int dim,
+                            double L, double *qw, double *env);
+// From the stored rows of rho (deposited with charges qw, S = 1, the origin
+// included): expand to the full cube (X), solve M phi = rho / eps0 by the
+// separable eigenbases (Vf[j M + i] = V[j][i], Vb[j M + i] = V[i][j], lam), and
+// write psi, the force table, psi0 and the (W, max|rho|) block partials.
+template <typename T>
+hipError_t launch_tent_solve(hipStream_t s, const double2 *rho, const Geom &g, int dim,
+                             const double *Vf, const double *Vb, const double *lam, double eps0,
+                             double2 *X, double2 *Y, double2 *psi, T *ftab, T *psi0,
+                             double *wpart, int *wblocks);
+// F = E F' - q grad(E) P, phi = E P from the force kernels' F' and P; v += kick F / m.
+hipError_t launch_tent_combine(hipStream_t s, const double *env, const double *q, const double *m,
+                               const double *Fk, const double *Pk, int64_t N, double kick,
+                               double *vel, double *F, double *phi);
 
 }  // namespace sce

@@ -22,6 +22,7 @@ SCE_OK, SCE_EINVAL, SCE_ENOMEM, SCE_EDEVICE, SCE_ESTATE, SCE_ENOTSUP, SCE_EUNSTA
 PREC = {"fp64": 0, "fp32": 1, "split_f16": 2}
 SCHEME = {"kdk": 0, "dkd": 1}
 SHAPE = {"delta": 0, "gaussian": 1, "tent": 2}
+FIELD = {"delta": 0, "tent": 1}
 
 _lib = None
 
@@ -101,6 +102,8 @@ def load_library():
         "sce_create": ([f64, i32, i32, f64, ctypes.POINTER(P)], i32),
         "sce_create_2d": ([f64, i32, i32, f64, ctypes.POINTER(P)], i32),
         "sce_dimension": ([P, ctypes.POINTER(i32)], i32),
+        "sce_create_tent": ([f64, i32, i32, ctypes.POINTER(P)], i32),
+        "sce_field_shape": ([P, ctypes.POINTER(i32)], i32),
         "sce_set_options": ([P, f64, i32, i32, P], i32),
         "sce_set_particles": ([P, i64, P, P, P, P, i32], i32),
         "sce_get_particles": ([P, P, P, i32], i32),
@@ -167,20 +170,29 @@ def _ptr(a):
 
 class Context:
     """One simulation context (``sce_ctx``); ``dim`` = 2 makes a two-dimensional
-    one (``sce_create_2d``), whose particle vectors are [2, N]."""
+    one (``sce_create_2d``), whose particle vectors are [2, N]; ``field`` =
+    "tent" makes a tent-field context (``sce_create_tent``: point particles,
+    ``shape`` and ``width`` must be "delta" and 0)."""
 
     def __init__(self, L: float, n_max: int, shape: str = "gaussian", width: float = 0.0,
-                 dim: int = 3):
+                 dim: int = 3, field: str = "delta"):
         self._lib = load_library()
         h = ctypes.c_void_p()
         if dim not in (2, 3):
             raise ValueError("dim must be 2 or 3")
-        create = self._lib.sce_create_2d if dim == 2 else self._lib.sce_create
-        st = create(float(L), int(n_max), SHAPE[shape], float(width), ctypes.byref(h))
+        if field == "tent":
+            if shape != "delta" or width != 0.0:
+                raise ValueError("tent-field contexts take point particles (shape 'delta', width 0)")
+            st = self._lib.sce_create_tent(float(L), int(n_max), int(dim), ctypes.byref(h))
+        elif field == "delta":
+            create = self._lib.sce_create_2d if dim == 2 else self._lib.sce_create
+            st = create(float(L), int(n_max), SHAPE[shape], float(width), ctypes.byref(h))
+        else:
+            raise ValueError("field must be 'delta' or 'tent'")
         if st != SCE_OK:
             raise SceError(st, "sce_create: " + self._lib.sce_status_string(st).decode())
         self._h = h
-        self.L, self.n_max, self.N, self.dim = float(L), int(n_max), 0, int(dim)
+        self.L, self.n_max, self.N, self.dim, self.field = float(L), int(n_max), 0, int(dim), field
 
     def _chk(self, st: int, what: str):
         if st != SCE_OK:
@@ -215,6 +227,11 @@ class Context:
         d = ctypes.c_int32()
         self._chk(self._lib.sce_dimension(self._h, ctypes.byref(d)), "sce_dimension")
         return int(d.value)
+
+    def sce_field_shape(self) -> str:
+        f = ctypes.c_int32()
+        self._chk(self._lib.sce_field_shape(self._h, ctypes.byref(f)), "sce_field_shape")
+        return {v: k for k, v in FIELD.items()}[int(f.value)]
 
     def sce_set_particles(self, x, v, q, m):
         """x, v: [dim, N]; q, m: [N]; numpy (host) or torch CUDA tensors (device)."""
@@ -332,7 +349,7 @@ class Context:
     @classmethod
     def from_particles(cls, p, precision: str = "fp64", scheme: str = "kdk", device: bool = False):
         """Context for a ``workloads.Particles`` record, particles already set."""
-        c = cls(p.L, p.n_max, p.shape, p.a, dim=getattr(p, "dim", 3))
+        c = cls(p.L, p.n_max, p.shape, p.a, dim=getattr(p, "dim", 3), field=getattr(p, "field", "delta"))
         c.sce_set_options(p.eps0, precision, scheme)
         if device:
             import torch

@@ -20,7 +20,8 @@ def _lib():
 
 def test_header_declares_the_api():
     names = sce.exported_symbols()
-    for required in ("sce_create", "sce_create_2d", "sce_dimension", "sce_set_step_graph", "sce_set_options", "sce_set_particles", "sce_get_particles",
+    for required in ("sce_create", "sce_create_2d", "sce_create_tent", "sce_field_shape",
+                     "sce_dimension", "sce_set_step_graph", "sce_set_options", "sce_set_particles", "sce_get_particles",
                      "sce_mode_count", "sce_modes", "sce_deposit", "sce_psi", "sce_force",
                      "sce_step", "sce_diagnostics", "sce_get_state", "sce_set_state", "sce_sync",
                      "sce_timing_enable", "sce_timing_read", "sce_destroy", "sce_status_string",
@@ -58,6 +59,12 @@ def test_invalid_create_arguments_are_rejected_on_host():
     assert lib.sce_create_2d(1.0, 8, 1, 0.05, None) == sce.SCE_EINVAL
     d = ctypes.c_int32()
     assert lib.sce_dimension(None, ctypes.byref(d)) == sce.SCE_EINVAL
+    for L, n, dim in [(-1.0, 8, 3), (float("nan"), 8, 3), (1.0, 0, 3), (1.0, 65, 2), (1.0, 8, 1),
+                      (1.0, 8, 4)]:
+        assert lib.sce_create_tent(L, n, dim, ctypes.byref(h)) == sce.SCE_EINVAL, (L, n, dim)
+        assert not h.value
+    assert lib.sce_create_tent(1.0, 8, 3, None) == sce.SCE_EINVAL
+    assert lib.sce_field_shape(None, ctypes.byref(d)) == sce.SCE_EINVAL
 
 
 def test_null_context_is_rejected():

@@ -41,6 +41,14 @@ z fields are zero and unused) follow the paper's own test settings:
                        physical values are not self-consistent and are not taken.
 * ``random_plasma_2d``, ``cold_lattice_2d``, ``random_particles_2d`` -- the 2-D
                        counterparts of the 3-D generators.
+
+Tent-field records (``field = "tent"``: finite-width field shapes on all of
+R^D, point particles, no periodic box):
+
+* ``tent_plasma``   -- a neutral plasma of point charges, uniform in the
+                       central cube [-L/4, L/4]^D where the basis envelope is
+                       largest, alternating +/-1, Maxwellian velocities, in 2-D
+                       or 3-D.
 """
 from __future__ import annotations
 
@@ -53,7 +61,7 @@ ROOT_SEED = 20150828  # arXiv submission date of the paper, used as a fixed root
 
 # index of each named workload in the root seed's spawned children
 _STREAM = {"two_body": 0, "random_plasma": 1, "cold_lattice": 2,
-           "two_species": 3, "serving": 4, "misc": 5, "two_d": 6}
+           "two_species": 3, "serving": 4, "misc": 5, "two_d": 6, "tent": 7}
 
 
 def _rng(name: str, salt: int = 0) -> np.random.Generator:
@@ -84,6 +92,7 @@ class Particles:
     n_steps: int = 1
     name: str = ""
     dim: int = 3              # 2: line charges in the periodic square, z unused
+    field: str = "delta"      # "tent": finite-width field shapes, open domain, point particles
 
     @property
     def N(self) -> int:
@@ -378,3 +387,27 @@ def grid_particles_2d(G: int, L: float = 1.0, salt: int = 0) -> Particles:
     z = np.zeros(G * G)
     return _make2(i.ravel() * L / G, j.ravel() * L / G, z, z, q, np.ones(G * G), L=L,
                   name=f"grid2d_{G}")
+
+
+def tent_plasma(N: int = 4096, n_max: int = 8, dim: int = 3, L: float = 1.0, half: float = 0.25,
+                sigma_v: float = 0.01, dt: float | None = None, n_steps: int = 100,
+                salt: int = 0) -> Particles:
+    """Neutral plasma of N point charges for the tent-field variant: positions
+    uniform in [-half L, half L]^dim (the envelope of the basis functions peaks
+    at the origin and vanishes at |x_d| = L), charges alternating +1 / -1, unit
+    masses, Maxwellian velocities of spread sigma_v, eps0 = 1.  The default step
+    is dt = 0.1 / omega_p, omega_p^2 = N / (2 half L)^dim (unit q, m, eps0)."""
+    if dt is None:
+        dt = 0.1 / math.sqrt(N / (2.0 * half * L) ** dim)
+    g = _rng("tent", salt)
+    pos = g.uniform(-half * L, half * L, size=(3, N))
+    vel = g.normal(0.0, sigma_v, size=(3, N))
+    q = np.where(np.arange(N) % 2 == 0, 1.0, -1.0)
+    m = np.ones(N)
+    if dim == 2:
+        return _make2(pos[0], pos[1], vel[0], vel[1], q, m, L=L, n_max=n_max, shape="delta", a=0.0,
+                      eps0=1.0, dt=dt, n_steps=n_steps, name=f"tent_plasma_2d_{N}_n{n_max}",
+                      field="tent")
+    return _make(pos[0], pos[1], pos[2], vel[0], vel[1], vel[2], q, m, L=L, n_max=n_max,
+                 shape="delta", a=0.0, eps0=1.0, dt=dt, n_steps=n_steps,
+                 name=f"tent_plasma_{N}_n{n_max}", field="tent")
