@@ -199,12 +199,23 @@ sce_status sce_psi(sce_ctx ctx, double *psi, int32_t on_device);
 sce_status sce_force(sce_ctx ctx, double *F, int32_t on_device);
 
 /* Advance n_steps >= 0 steps of size dt (finite) with the configured scheme.
- * With n_steps >= 2 G (G = steps per graph, see sce_set_step_graph) and
+ * Small FP64 systems run as one kernel per block of steps (sce_set_small_step).
+ * Otherwise, with n_steps >= 2 G (G = steps per graph, see sce_set_step_graph) and
  * timing off, the first step runs directly, then blocks of G steps replay a
  * HIP graph of their launches (captured again whenever dt, the scheme, the
  * particles or the options change), then the rest run directly.  Results are
  * identical to launching every step directly. */
 sce_status sce_step(sce_ctx ctx, double dt, int64_t n_steps);
+
+/* Small systems: sce_step runs an FP64, delta-field context with N <= 256,
+ * |H| <= 3072, N (n_max + 1) <= 1024 and N |H| <= max_pairs as one
+ * single-workgroup kernel per block of up to 4096 steps (the phase tables,
+ * deposit, solve, force, kicks and drift of every step as stages of one
+ * launch, the state kept on chip), unless kernel timing is enabled.  Such a
+ * step is otherwise bound by the latency of its five kernels.  Results agree
+ * with the multi-kernel step to rounding (not bit for bit).  max_pairs in
+ * 0..2^24 (0: never; default 65536).  SCE_EINVAL outside the range. */
+sce_status sce_set_small_step(sce_ctx ctx, int64_t max_pairs);
 
 /* Steps per captured graph for sce_step, 0..4096 (0: launch every step
  * directly; default 8).  Replaying a graph removes the host's per-launch

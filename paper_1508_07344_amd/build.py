@@ -17,8 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsce.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "kernels_mfma.hip", "kernels_serve.hip", "kernels_tent.hip", "sce_api.hip",
-           "sce_server.hip"]
+SOURCES = ["kernels.hip", "kernels_mfma.hip", "kernels_serve.hip", "kernels_tent.hip",
+           "kernels_small.hip", "sce_api.hip", "sce_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

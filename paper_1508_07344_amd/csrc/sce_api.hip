@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -72,6 +73,11 @@ struct sce_ctx_s {
     double2 *cubeX = nullptr, *cubeY = nullptr;
     double *Vf = nullptr, *Vb = nullptr, *lam = nullptr;
     double env_max = 1.0;  // E(0), the largest envelope value
+    // small systems: the stored modes as integer triplets and S^2 / (eps0 k^2 V),
+    // for the single-workgroup multi-step kernel (|H| <= kSmallMaxH only)
+    short4 *smodes = nullptr;
+    double *sweight = nullptr;
+    int64_t small_max_pairs = 1 << 16;  // largest N |H| stepped by that kernel (0: never)
 
     bool fields_valid = false;  // rho/psi/W/ftab correspond to the current positions
     bool force_valid = false;   // F corresponds to the current positions
@@ -222,6 +228,35 @@ sce_status build_tables(sce_ctx c)
         }
     }
     c->self_sum = self;
+    if (c->field != SCE_FIELD_TENT && g.H <= sce::kSmallMaxH) {
+        std::vector<short4> md;
+        std::vector<double> wt;
+        md.reserve(g.H);
+        wt.reserve(g.H);
+        for (int r = 0; r < g.R; ++r) {
+            int nx, ny;
+            sce::row_nxny(r, g.n, nx, ny);
+            for (int nz = -g.n; nz <= g.n; ++nz) {
+                if (!sce::in_half(nx, ny, nz)) continue;
+                const double kx = f * nx, ky = f * ny, kz = f * nz;
+                const double k2 = kx * kx + ky * ky + kz * kz;
+                const double s = shape_factor(c->kind, c->width, kx, ky, kz);
+                short4 v;
+                v.x = (short)nx;
+                v.y = (short)ny;
+                v.z = (short)nz;
+                v.w = 0;
+                md.push_back(v);
+                wt.push_back(s * s / (c->eps0 * k2 * V));
+            }
+        }
+        if (!c->smodes) {
+            HIPCHK(c, dev_alloc(c->smodes, g.H * sizeof(short4)));
+            HIPCHK(c, dev_alloc(c->sweight, g.H * sizeof(double)));
+        }
+        HIPCHK(c, hipMemcpy(c->smodes, md.data(), g.H * sizeof(short4), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->sweight, wt.data(), g.H * sizeof(double), hipMemcpyHostToDevice));
+    }
     if (!c->Stab) {
         HIPCHK(c, dev_alloc(c->Stab, cnt * sizeof(double)));
         HIPCHK(c, dev_alloc(c->Gtab, cnt * sizeof(double)));
@@ -962,6 +997,24 @@ sce_status sce_step(sce_ctx c, double dt, int64_t n_steps)
     if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
     if (!std::isfinite(dt)) return fail(c, SCE_EINVAL, "dt must be finite");
     if (n_steps < 0) return fail(c, SCE_EINVAL, "n_steps must be >= 0");
+    if (c->smodes && c->field == SCE_FIELD_DELTA && c->prec == SCE_PREC_FP64 && !c->timing &&
+        n_steps > 0 && c->N <= sce::kSmallMaxN && c->N * 3 * (c->g.n + 1) <= sce::kSmallMaxTab &&
+        c->N * c->g.H <= c->small_max_pairs) {
+        const bool kdk = c->scheme == SCE_SCHEME_KDK;
+        if (kdk && !c->force_valid && (st = pass(c, 0.0))) return st;
+        for (int64_t s = 0; s < n_steps;) {
+            const int chunk = (int)std::min<int64_t>(n_steps - s, 4096);
+            HIPCHK(c, sce::launch_step_small(c->stream, c->pos, c->vel, c->F, c->q, c->m, c->N,
+                                             c->smodes, c->sweight, c->g, c->L, dt, chunk, kdk));
+            s += chunk;
+            c->step += chunk;
+            c->time += chunk * dt;
+        }
+        c->fields_valid = false;
+        c->force_valid = kdk;
+        c->phi_valid = false;
+        return SCE_OK;
+    }
     int64_t s = 0;
     const int G = c->graph_steps;
     if (G > 0 && !c->timing && n_steps >= 2 * (int64_t)G) {
@@ -979,6 +1032,16 @@ sce_status sce_step(sce_ctx c, double dt, int64_t n_steps)
     }
     for (; s < n_steps; ++s)
         if ((st = step_once(c, dt))) return st;
+    return SCE_OK;
+}
+
+sce_status sce_set_small_step(sce_ctx c, int64_t max_pairs)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (max_pairs < 0 || max_pairs > ((int64_t)1 << 24))
+        return fail(c, SCE_EINVAL, "max_pairs must be in 0..2^24");
+    c->small_max_pairs = max_pairs;
     return SCE_OK;
 }
 
@@ -1193,6 +1256,8 @@ void sce_destroy(sce_ctx c)
     free_devp(c->Vf);
     free_devp(c->Vb);
     free_devp(c->lam);
+    free_devp(c->smodes);
+    free_devp(c->sweight);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

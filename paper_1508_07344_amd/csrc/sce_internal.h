@@ -141,6 +141,19 @@ hipError_t launch_diag(hipStream_t s, const double *vel, const double *q, const 
                        const double *phi, int64_t N, const double *wpart, int wblocks,
                        double eps0V, double *scratch, double *out);
 
+// ---- small systems: many steps in one single-workgroup launch (kernels_small.hip)
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallMaxN = 256;     // particles
+constexpr int kSmallMaxH = 3072;    // stored modes
+constexpr int kSmallMaxTab = 3072;  // phase-table entries N * 3 * (n + 1)
+// steps KDK (kdk) or DKD steps of size dt; modes: the stored half space as
+// (n_x, n_y, n_z, 0) in canonical order, wmode = S^2 / (eps0 |k|^2 V) per mode;
+// F must hold the force at the current positions for KDK and holds the force
+// of the last evaluation afterwards.
+hipError_t launch_step_small(hipStream_t s, double *pos, double *vel, double *F, const double *q,
+                             const double *m, int64_t N, const short4 *modes, const double *wmode,
+                             const Geom &g, double L, double dt, int steps, bool kdk);
+
 // ---- finite-width tent field shapes, point particles (kernels_tent.hip)
 // Envelope E(x), its gradient (env [4][N]: E, dE/dx, dE/dy, dE/dz) and the
 // weighted charges qw = q E; dim 2 spans only the stored y and z.

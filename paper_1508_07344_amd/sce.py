@@ -114,6 +114,7 @@ def load_library():
         "sce_force": ([P, P, i32], i32),
         "sce_step": ([P, f64, i64], i32),
         "sce_set_step_graph": ([P, i32], i32),
+        "sce_set_small_step": ([P, i64], i32),
         "sce_diagnostics": ([P, ctypes.POINTER(_Diag), P], i32),
         "sce_get_state": ([P, P, ctypes.POINTER(ctypes.c_size_t)], i32),
         "sce_set_state": ([P, P, ctypes.c_size_t], i32),
@@ -308,6 +309,9 @@ class Context:
 
     def sce_set_step_graph(self, steps_per_graph: int):
         self._chk(self._lib.sce_set_step_graph(self._h, int(steps_per_graph)), "sce_set_step_graph")
+
+    def sce_set_small_step(self, max_pairs: int):
+        self._chk(self._lib.sce_set_small_step(self._h, int(max_pairs)), "sce_set_small_step")
 
     def sce_diagnostics(self, rho_abs: bool = False, allow_unstable: bool = False):
         d = _Diag()

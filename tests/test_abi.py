@@ -21,7 +21,7 @@ def _lib():
 def test_header_declares_the_api():
     names = sce.exported_symbols()
     for required in ("sce_create", "sce_create_2d", "sce_create_tent", "sce_field_shape",
-                     "sce_dimension", "sce_set_step_graph", "sce_set_options", "sce_set_particles", "sce_get_particles",
+                     "sce_dimension", "sce_set_step_graph", "sce_set_small_step", "sce_set_options", "sce_set_particles", "sce_get_particles",
                      "sce_mode_count", "sce_modes", "sce_deposit", "sce_psi", "sce_force",
                      "sce_step", "sce_diagnostics", "sce_get_state", "sce_set_state", "sce_sync",
                      "sce_timing_enable", "sce_timing_read", "sce_destroy", "sce_status_string",
@@ -72,6 +72,7 @@ def test_null_context_is_rejected():
     assert lib.sce_sync(None) == sce.SCE_EINVAL
     assert lib.sce_step(None, 1e-3, 1) == sce.SCE_EINVAL
     assert lib.sce_set_step_graph(None, 8) == sce.SCE_EINVAL
+    assert lib.sce_set_small_step(None, 0) == sce.SCE_EINVAL
     assert lib.sce_deposit(None, None, 0) == sce.SCE_EINVAL
     lib.sce_destroy(None)  # no-op
 

@@ -24,6 +24,7 @@ def _gpu():
 def _run(sce, p, prec, scheme, graph):
     out = []
     with sce.Context.from_particles(p, precision=prec, scheme=scheme) as c:
+        c.sce_set_small_step(0)  # the multi-kernel step, whose launches the graph replays
         c.sce_set_step_graph(graph)
         for n, dt in ((37, p.dt), (1, p.dt), (50, p.dt), (33, 0.5 * p.dt), (40, p.dt)):
             c.sce_step(dt, n)
@@ -60,6 +61,7 @@ def test_graph_replay_costs_no_time_on_small_systems():
     rates = {}
     for G in (0, 8, 32):
         with sce.Context.from_particles(p) as c:
+            c.sce_set_small_step(0)
             c.sce_set_step_graph(G)
             c.sce_step(p.dt, 200)
             c.sce_sync()
