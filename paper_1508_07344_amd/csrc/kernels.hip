@@ -396,29 +396,56 @@ __device__ inline double block_max(double v, double *sh)
     return t;
 }
 
+// A block covers 64 cells (row, n_z) with kReduceWays waves: wave p sums the
+// splits p, p + kReduceWays, ... of each of its lane's cell (the reads of a
+// wave are 64 consecutive rows), and the ways are then added in a fixed order
+// through LDS, so the result does not depend on scheduling.  One thread per
+// cell and all splits in one loop left most compute units idle at n_max = 16
+// (37 blocks) while the loop streamed the partials.
+constexpr int kReduceWays = 8;
+
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kReduceWays)
 k_reduce_solve(const double *__restrict__ part, int splits, int n, int R, int Rpad, int nzp,
                const double *__restrict__ Stab, const double *__restrict__ Gtab,
                const double *__restrict__ Ktab, double2 *__restrict__ rho,
                double2 *__restrict__ psi, T *__restrict__ ftab, T *__restrict__ psi0,
                double *__restrict__ wpart)
 {
-    __shared__ double sh[8];
+    __shared__ double4 ways[kReduceWays][64];
     const int n1 = n + 1, M = 2 * n + 1;
-    const int64_t cell = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63, way = threadIdx.x >> 6;
+    const int64_t cell = (int64_t)blockIdx.x * 64 + lane;
+    const bool valid = cell < (int64_t)n1 * R;
+    {
+        double Pr = 0.0, Pi = 0.0, Qr = 0.0, Qi = 0.0;
+        if (valid) {
+            const int nz = (int)(cell / R);
+            const int row = (int)(cell - (int64_t)nz * R);
+            const int64_t sstride = (int64_t)n1 * 4 * Rpad;
+            const double *pp = part + (int64_t)way * sstride + (int64_t)nz * 4 * Rpad + row;
+            for (int sp = way; sp < splits; sp += kReduceWays, pp += kReduceWays * sstride) {
+                Pr += pp[0];
+                Pi += pp[Rpad];
+                Qr += pp[2 * (int64_t)Rpad];
+                Qi += pp[3 * (int64_t)Rpad];
+            }
+        }
+        ways[way][lane] = make_double4(Pr, Pi, Qr, Qi);
+    }
+    __syncthreads();
+    if (way != 0) return;
     double w = 0.0, amax = 0.0;
-    if (cell < (int64_t)n1 * R) {
+    if (valid) {
         const int nz = (int)(cell / R);
         const int row = (int)(cell - (int64_t)nz * R);
-        const int64_t sstride = (int64_t)n1 * 4 * Rpad;
-        const double *pp = part + (int64_t)nz * 4 * Rpad + row;
         double Pr = 0.0, Pi = 0.0, Qr = 0.0, Qi = 0.0;
-        for (int sp = 0; sp < splits; ++sp, pp += sstride) {
-            Pr += pp[0];
-            Pi += pp[Rpad];
-            Qr += pp[2 * (int64_t)Rpad];
-            Qi += pp[3 * (int64_t)Rpad];
+        for (int p = 0; p < kReduceWays; ++p) {
+            const double4 v = ways[p][lane];
+            Pr += v.x;
+            Pi += v.y;
+            Qr += v.z;
+            Qi += v.w;
         }
         int nx, ny;
         row_nxny(row, n, nx, ny);
@@ -461,11 +488,14 @@ k_reduce_solve(const double *__restrict__ part, int splits, int n, int R, int Rp
             f[7] = (T)(nz * si);
         }
     }
-    const double ws = block_sum(w, sh);
-    const double wm = block_max(amax, sh);
-    if (threadIdx.x == 0) {
-        wpart[2 * blockIdx.x] = ws;
-        wpart[2 * blockIdx.x + 1] = wm;
+    // the block's W and max|rho| over its 64 cells (one wave, fixed order)
+    for (int o = 32; o > 0; o >>= 1) {
+        w += __shfl_xor(w, o, 64);
+        amax = fmax(amax, __shfl_xor(amax, o, 64));
+    }
+    if (lane == 0) {
+        wpart[2 * blockIdx.x] = w;
+        wpart[2 * blockIdx.x + 1] = amax;
     }
 }
 
@@ -476,9 +506,9 @@ hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, co
                                int *wblocks)
 {
     const int64_t cells = (int64_t)(g.n + 1) * g.R;
-    const int blocks = (int)((cells + 255) / 256);
+    const int blocks = (int)((cells + 63) / 64);
     *wblocks = blocks;
-    hipLaunchKernelGGL(k_reduce_solve<T>, dim3(blocks), dim3(256), 0, s, part, splits, g.n, g.R,
+    hipLaunchKernelGGL(k_reduce_solve<T>, dim3(blocks), dim3(64 * kReduceWays), 0, s, part, splits, g.n, g.R,
                        g.Rpad, g.nzp, Stab, Gtab, Ktab, rho, psi, ftab, psi0, wpart);
     return hipGetLastError();
 }

@@ -691,19 +691,26 @@ __global__ void __launch_bounds__(256)
 k_force_rows(const float *__restrict__ ftab, const float *__restrict__ psi0, int n, int lines,
              int nzp, float4 *__restrict__ rinfo)
 {
+    // one wave per padded row: the row's table entries read by the 64 lanes
+    // together, their largest magnitude by a butterfly
     const ForceQuads f = force_quads(n, lines);
-    const int pr = blockIdx.x * 256 + threadIdx.x;
+    const int pr = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (pr >= 4 * f.Qpad) return;
     int nx = 0, ny = 0;
     const int r = force_row(pr, n, f, nx, ny);
     if (r < 0) {
-        rinfo[2 * pr] = make_float4(0.f, 0.f, 0.f, 0.f);
-        rinfo[2 * pr + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (lane == 0) {
+            rinfo[2 * pr] = make_float4(0.f, 0.f, 0.f, 0.f);
+            rinfo[2 * pr + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
         return;
     }
     float m = 0.f;
     const float *fr = ftab + (int64_t)r * nzp * 8;
-    for (int i = 0; i < n * 8; ++i) m = fmaxf(m, fabsf(fr[i]));
+    for (int i = lane; i < n * 8; i += 64) m = fmaxf(m, fabsf(fr[i]));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if (lane != 0) return;
     const float pre = psi0[2 * r], pim = psi0[2 * r + 1];
     m = fmaxf(m, ldexpf(fmaxf(fabsf(pre), fabsf(pim)), -60));
     int e = 0;
@@ -772,7 +779,7 @@ hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0
                              float4 *rinfo, _Float16 *wf)
 {
     const ForceQuads f = force_quads(g.n, g.lines);
-    hipLaunchKernelGGL(k_force_rows, dim3((4 * f.Qpad + 255) / 256), dim3(256), 0, s, ftab, psi0, g.n,
+    hipLaunchKernelGGL(k_force_rows, dim3((unsigned)f.Qpad), dim3(256), 0, s, ftab, psi0, g.n,
                        g.lines, g.nzp, rinfo);
     const int nzk = (g.n + 15) / 16 * 16;
     const int ks = nzk / 16;

@@ -704,7 +704,7 @@ sce_status create_ctx(double L, int32_t n_max, int32_t shape_kind, double shape_
         const Geom &g = c->g;
         if (dev_alloc(c->rho, g.P * sizeof(double2)) != hipSuccess ||
             dev_alloc(c->psi, g.P * sizeof(double2)) != hipSuccess ||
-            dev_alloc(c->wpart, ((size_t)g.n1 * g.R / 256 + 2) * 2 * sizeof(double)) != hipSuccess ||
+            dev_alloc(c->wpart, ((size_t)g.n1 * g.R / 64 + 2) * 2 * sizeof(double)) != hipSuccess ||
             dev_alloc(c->dout, 8 * sizeof(double)) != hipSuccess)
             st = SCE_ENOMEM;
     }

@@ -84,7 +84,8 @@ hipError_t launch_deposit(hipStream_t s, const double2 *exy, const T *tz, const 
                           const Geom &g, const DepositPlan &pl, double *part);
 
 // Sum the partials over splits in fixed order, form rho and psi on the padded
-// layout, the force table and the per-block (W, max|rho|) partials.
+// layout, the force table and the per-block (W, max|rho|) partials (one block
+// per 64 cells (row, n_z); wpart holds 2 doubles per block).
 // ftab layout [R][nzp][8] of T: (sig_re, sig_im, del_re, del_im, nz del_re,
 // nz del_im, nz sig_re, nz sig_im) for n_z = 1..nzp with sig = psi(+nz) + psi(-nz),
 // del = psi(+nz) - psi(-nz); psi0 [R][2]: psi at n_z = 0.
