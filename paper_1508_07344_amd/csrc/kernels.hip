@@ -514,33 +514,19 @@ hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, co
 }
 
 // ------------------------------------------------------------------ force
-// One particle per lane.  Rows are visited in the same order by every lane,
-// so the force table entries of a row are wave-uniform (scalar loads); the
-// lane's cos/sin(n_z tz) for a chunk of NZC values stay in registers.  PLANE:
-// a two-dimensional context (rows of n_x = 0 only).  The number of n_x lines
-// is a compile-time choice on purpose: the row loop is bound by the latency
-// of the table's scalar loads, which the compiler hides by double-buffering
-// them in SGPRs, and one more live scalar (a runtime line count) leaves no
-// room for the second buffer (measured: FP64 force 37 -> 55 ms at 2^20
-// particles, n_max = 32).
-template <typename T, int NZC, bool PLANE>
-__global__ void __launch_bounds__(256)
-k_force(const double *__restrict__ pos, const double *__restrict__ q,
-        const double *__restrict__ m, double *__restrict__ vel, const T *__restrict__ ftab,
-        const T *__restrict__ psi0, int n, int nzp, double invL, int64_t N,
-        double kick, double *__restrict__ F, double *__restrict__ phi)
+// The sums of one lane's particle over the rows of the n_x lines [l0, l1)
+// (r0: the row index of line l0's first row): fx, fy, fz, ph before the
+// factor 2 q (2 pi / L).
+template <typename T, int NZC>
+__device__ __forceinline__ void force_line_sums(const T *__restrict__ ftab, const T *__restrict__ psi0,
+                                                int n, int nzp, int l0, int l1, int r0, double tx,
+                                                double ty, double tz, double &fx, double &fy,
+                                                double &fz, double &ph)
 {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t jc = j < N ? j : N - 1;
-    const double tx = frac(pos[jc] * invL);
-    const double ty = frac(pos[N + jc] * invL);
-    const double tz = frac(pos[2 * N + jc] * invL);
     double eyc, eys;
     cis_turns(ty, eyc, eys);
     double ezc, ezs;
     cis_turns(tz, ezc, ezs);
-    double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
-
     for (int c0 = 0; c0 < nzp; c0 += NZC) {
         T cz[NZC], sz[NZC];
         {
@@ -558,8 +544,8 @@ k_force(const double *__restrict__ pos, const double *__restrict__ q,
                 sz[k] = (T)s;
             }
         }
-        int r = 0;
-        for (int nx = 0; nx <= (PLANE ? 0 : n); ++nx) {
+        int r = r0;
+        for (int nx = l0; nx < l1; ++nx) {
             const int ny0 = nx == 0 ? 0 : -n;
             double hc, hs;
             cis_turns(frac_lin(nx, tx, ny0, ty), hc, hs);
@@ -595,6 +581,31 @@ k_force(const double *__restrict__ pos, const double *__restrict__ q,
             }
         }
     }
+}
+
+// One particle per lane.  Rows are visited in the same order by every lane,
+// so the force table entries of a row are wave-uniform (scalar loads); the
+// lane's cos/sin(n_z tz) for a chunk of NZC values stay in registers.  PLANE:
+// a two-dimensional context (rows of n_x = 0 only).  The number of n_x lines
+// is a compile-time choice on purpose: the row loop is bound by the latency
+// of the table's scalar loads, which the compiler hides by double-buffering
+// them in SGPRs, and one more live scalar (a runtime line count) leaves no
+// room for the second buffer (measured: FP64 force 37 -> 55 ms at 2^20
+// particles, n_max = 32).
+template <typename T, int NZC, bool PLANE>
+__global__ void __launch_bounds__(256)
+k_force(const double *__restrict__ pos, const double *__restrict__ q,
+        const double *__restrict__ m, double *__restrict__ vel, const T *__restrict__ ftab,
+        const T *__restrict__ psi0, int n, int nzp, double invL, int64_t N,
+        double kick, double *__restrict__ F, double *__restrict__ phi)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t jc = j < N ? j : N - 1;
+    const double tx = frac(pos[jc] * invL);
+    const double ty = frac(pos[N + jc] * invL);
+    const double tz = frac(pos[2 * N + jc] * invL);
+    double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
+    force_line_sums<T, NZC>(ftab, psi0, n, nzp, 0, PLANE ? 1 : n + 1, 0, tx, ty, tz, fx, fy, fz, ph);
     if (j < N) {
         const double f = 2.0 * q[j] * (6.283185307179586476925286766559 * invL);
         fx *= f;
@@ -612,6 +623,68 @@ k_force(const double *__restrict__ pos, const double *__restrict__ q,
             vel[N + j] += a * fy;
             vel[2 * N + j] += a * fz;
         }
+    }
+}
+
+// Medium particle counts (too few blocks of 256 particles to fill the compute
+// units): blockIdx.y takes the n_x lines [y L / S, (y + 1) L / S) of L lines,
+// S = gridDim.y, and writes its raw sums to part[y][4][N] (fx, fy, fz, ph);
+// k_force_combine adds the S line groups in order, scales and kicks.
+template <typename T, int NZC>
+__global__ void __launch_bounds__(256)
+k_force_lines(const double *__restrict__ pos, const T *__restrict__ ftab,
+              const T *__restrict__ psi0, int n, int lines, int nzp, double invL, int64_t N,
+              double *__restrict__ part)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t jc = j < N ? j : N - 1;
+    const int S = gridDim.y, y = blockIdx.y;
+    const int l0 = y * lines / S, l1 = (y + 1) * lines / S;
+    const int r0 = l0 == 0 ? 0 : (n + 1) + (l0 - 1) * (2 * n + 1);
+    const double tx = frac(pos[jc] * invL);
+    const double ty = frac(pos[N + jc] * invL);
+    const double tz = frac(pos[2 * N + jc] * invL);
+    double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
+    force_line_sums<T, NZC>(ftab, psi0, n, nzp, l0, l1, r0, tx, ty, tz, fx, fy, fz, ph);
+    if (j < N) {
+        double *o = part + (int64_t)y * 4 * N + j;
+        o[0] = fx;
+        o[N] = fy;
+        o[2 * N] = fz;
+        o[3 * N] = ph;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_force_combine(const double *__restrict__ part, int S, const double *__restrict__ q,
+                const double *__restrict__ m, double *__restrict__ vel, int64_t N, double invL,
+                double kick, double *__restrict__ F, double *__restrict__ phi)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
+    for (int y = 0; y < S; ++y) {
+        const double *o = part + (int64_t)y * 4 * N + j;
+        fx += o[0];
+        fy += o[N];
+        fz += o[2 * N];
+        ph += o[3 * N];
+    }
+    const double f = 2.0 * q[j] * (6.283185307179586476925286766559 * invL);
+    fx *= f;
+    fy *= f;
+    fz *= f;
+    if (F) {
+        F[j] = fx;
+        F[N + j] = fy;
+        F[2 * N + j] = fz;
+    }
+    if (phi) phi[j] = 2.0 * ph;
+    if (kick != 0.0) {
+        const double a = kick / m[j];
+        vel[j] += a * fx;
+        vel[N + j] += a * fy;
+        vel[2 * N + j] += a * fz;
     }
 }
 
@@ -725,10 +798,32 @@ hipError_t launch_force_chunk(hipStream_t s, const double *pos, const double *q,
     return hipGetLastError();
 }
 
+int force_line_groups(const Geom &g, int64_t N, int elem_bytes)
+{
+    if (N <= (elem_bytes == 8 ? force_small_max<double>() : force_small_max<float>())) return 1;
+    const int64_t blocks = (N + 255) / 256;
+    if (blocks >= kForceLineBlocks || g.lines < 2) return 1;
+    const int64_t want = (kForceLineBlocks + blocks - 1) / blocks;
+    return (int)(want < g.lines ? want : g.lines);
+}
+
+template <typename T, int NZC>
+hipError_t launch_force_lines(hipStream_t s, const double *pos, const double *q, const double *m,
+                              double *vel, const T *ftab, const T *psi0, const Geom &g, double L,
+                              int64_t N, double kick, double *F, double *phi, int S, double *part)
+{
+    const int64_t blocks = (N + 255) / 256;
+    hipLaunchKernelGGL((k_force_lines<T, NZC>), dim3((unsigned)blocks, (unsigned)S), dim3(256), 0, s, pos,
+                       ftab, psi0, g.n, g.lines, g.nzp, 1.0 / L, N, part);
+    hipLaunchKernelGGL(k_force_combine, dim3((unsigned)blocks), dim3(256), 0, s, part, S, q, m, vel, N,
+                       1.0 / L, kick, F, phi);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const double *m,
                         double *vel, const T *ftab, const T *psi0, const Geom &g, double L,
-                        int64_t N, double kick, double *F, double *phi)
+                        int64_t N, double kick, double *F, double *phi, double *part)
 {
     if (N <= force_small_max<T>()) {
         hipLaunchKernelGGL(k_force_small<T>, dim3((unsigned)N), dim3(256), 0, s, pos, q, m, vel, ftab,
@@ -736,6 +831,13 @@ hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const
         return hipGetLastError();
     }
     const int nzc = force_chunk(g.n, (int)sizeof(T));
+    const int S = force_line_groups(g, N, (int)sizeof(T));
+    if (S > 1) {
+        if (!part) return hipErrorInvalidValue;
+        if (nzc == 8) return launch_force_lines<T, 8>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi, S, part);
+        if (nzc == 16 || sizeof(T) == 8) return launch_force_lines<T, 16>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi, S, part);
+        if constexpr (sizeof(T) == 4) return launch_force_lines<T, 32>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi, S, part);
+    }
     if (g.lines == 1) {
         if (nzc == 8) return launch_force_chunk<T, 8, true>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi);
         if (nzc == 16 || sizeof(T) == 8) return launch_force_chunk<T, 16, true>(s, pos, q, m, vel, ftab, psi0, g, L, N, kick, F, phi);
@@ -868,7 +970,7 @@ template hipError_t launch_deposit<float>(hipStream_t, const double2 *, const fl
 template hipError_t launch_deposit<double>(hipStream_t, const double2 *, const double *, const double *, int64_t, const Geom &, const DepositPlan &, double *);
 template hipError_t launch_reduce_solve<float>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, float *, float *, double *, int *);
 template hipError_t launch_reduce_solve<double>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, double *, double *, double *, int *);
-template hipError_t launch_force<float>(hipStream_t, const double *, const double *, const double *, double *, const float *, const float *, const Geom &, double, int64_t, double, double *, double *);
-template hipError_t launch_force<double>(hipStream_t, const double *, const double *, const double *, double *, const double *, const double *, const Geom &, double, int64_t, double, double *, double *);
+template hipError_t launch_force<float>(hipStream_t, const double *, const double *, const double *, double *, const float *, const float *, const Geom &, double, int64_t, double, double *, double *, double *);
+template hipError_t launch_force<double>(hipStream_t, const double *, const double *, const double *, double *, const double *, const double *, const Geom &, double, int64_t, double, double *, double *, double *);
 
 }  // namespace sce

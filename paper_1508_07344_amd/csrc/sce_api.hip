@@ -66,6 +66,8 @@ struct sce_ctx_s {
     int wblocks = 0;
     double *dscratch = nullptr;
     size_t dscratch_bytes = 0;
+    double *fscratch = nullptr;  // line-group partial sums of the VALU force
+    size_t fscratch_bytes = 0;
     double *dout = nullptr;
     // tent field shapes: weighted charges, envelope [4][N], force-kernel F and
     // P before the envelope, the mode cube (two buffers), the 1-D eigenbases
@@ -520,9 +522,16 @@ sce_status run_force(sce_ctx c, double kick)
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
     const bool tent = c->field == SCE_FIELD_TENT;
+    const int lg = sce::force_line_groups(c->g, c->N, (int)sizeof(T));
+    if (lg > 1) {
+        void *fs = c->fscratch;
+        sce_status st = ensure_bytes(c, fs, c->fscratch_bytes, (size_t)lg * 4 * c->N * sizeof(double));
+        c->fscratch = (double *)fs;
+        if (st) return st;
+    }
     HIPCHK(c, sce::launch_force<T>(c->stream, c->pos, c->q, c->m, c->vel, (const T *)c->ftab,
                                    (const T *)c->psi0, c->g, c->L, c->N, tent ? 0.0 : kick,
-                                   tent ? c->Fk : c->F, tent ? c->Pk : c->phi));
+                                   tent ? c->Fk : c->F, tent ? c->Pk : c->phi, c->fscratch));
     if (c->timing && ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_frc.push_back(ep);
@@ -1246,6 +1255,7 @@ void sce_destroy(sce_ctx c)
     free_devp(c->turns);
     free_devp(c->wpart);
     free_devp(c->dscratch);
+    free_devp(c->fscratch);
     free_devp(c->dout);
     free_devp(c->qw);
     free_devp(c->env);

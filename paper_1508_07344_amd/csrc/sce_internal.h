@@ -96,10 +96,16 @@ hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, co
                                int *wblocks);
 
 // Force (and potential) at the current positions; optional kick v += kick F/m.
+// Between the small-count kernel and kForceLineBlocks blocks of 256 particles
+// the n_x lines are split over force_line_groups(...) groups of blocks, whose
+// FP64 partial sums go to part ([groups][4][N] doubles, caller-owned) and are
+// then added in a fixed order.
+constexpr int kForceLineBlocks = 1024;
+int force_line_groups(const Geom &g, int64_t N, int elem_bytes);
 template <typename T>
 hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const double *m,
                         double *vel, const T *ftab, const T *psi0, const Geom &g, double L,
-                        int64_t N, double kick, double *F, double *phi);
+                        int64_t N, double kick, double *F, double *phi, double *part);
 
 // ---- split-precision matrix-core path (kernels_mfma.hip)
 struct MfmaDepositPlan {
