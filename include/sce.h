@@ -287,8 +287,12 @@ typedef struct {
     int32_t shape_kind;       /* sce_shape_kind */
     int64_t N;                /* particles, >= 1 */
     int64_t n_steps;          /* >= 0 */
-    const double *x, *v;      /* host [3][N]; positions outside [0, L) are wrapped by the first drift */
+    const double *x, *v;      /* host [3][N] ([2][N] when dim = 2); positions outside [0, L) are
+                                 wrapped by the first drift */
     const double *q, *m;      /* host [N]; m > 0 */
+    int32_t dim;              /* 3 (or 0): the periodic cube; 2: line charges in the periodic
+                                 square with the conventions of sce_create_2d (x, v and the
+                                 result's x, v, F are [2][N], the area L^2 replaces V) */
 } sce_request;
 
 typedef struct {
@@ -324,8 +328,8 @@ sce_status sce_server_tick(sce_server s, int32_t *n_active, int32_t *n_queued);
 /* Ids of requests finished since the last poll, oldest first, at most max. */
 sce_status sce_server_poll(sce_server s, uint64_t *done_ids, int32_t max, int32_t *n_done);
 
-/* Result of a finished request, then forgotten: x, v, F host [3][N] at the
- * end (F at the final positions), diagnostics at the start (first) and the
+/* Result of a finished request, then forgotten: x, v, F host [3][N] ([2][N]
+ * for a two-dimensional request) at the end (F at the final positions), diagnostics at the start (first) and the
  * end (last).  Any output may be NULL.  SCE_EINVAL if id is not finished or
  * was already fetched. */
 sce_status sce_server_result(sce_server s, uint64_t id, double *x, double *v, double *F,

@@ -245,7 +245,7 @@ k_serve_reduce(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
             const double kx = kf * nx, ky = kf * ny, kz = kf * nz;
             const double k2 = kx * kx + ky * ky + kz * kz;
             const double S = shape_at(d.shape, d.a, kx, ky, kz);
-            const double V = d.L * d.L * d.L;
+            const double V = d.dim == 2 ? d.L * d.L : d.L * d.L * d.L;
             const double K = k2 > 0.0 ? 1.0 / (d.eps0 * k2 * V) : 0.0;
             const double G = S * K;
             const double rpr = S * (Pr + Qi), rpi = S * (Pi - Qr);  // rho(+nz)
@@ -539,7 +539,7 @@ size_t serve_layout(ReqDesc &d, int elem_bytes)
 {
     const int n = d.n;
     const int64_t N = d.N;
-    d.R = (n + 1) + n * (2 * n + 1);
+    d.R = d.dim == 2 ? n + 1 : (n + 1) + n * (2 * n + 1);
     d.Rp = (d.R + 63) / 64 * 64;
     d.nzs = serve_nz(n);
     d.segs = (int)((N + kServeSeg - 1) / kServeSeg);

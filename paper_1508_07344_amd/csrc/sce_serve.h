@@ -38,6 +38,7 @@ struct ReqDesc {
     int64_t N;
     int n, R, Rp, nzs;       // n_max, rows, rows rounded up to 64, n_z slots (serve_nz)
     int segs, rblocks, fblocks, shape;
+    int dim;                 // 3, or 2: the n_x = 0 slice (rows 0..n), area L^2
     double L, invL, a, eps0, dt;
     int64_t pass, n_steps;   // pass: passes done (device-incremented at tick end)
     // byte offsets into the arena

@@ -45,10 +45,11 @@ struct Request {
 };
 
 struct Result {
-    std::vector<double> x, v, F;
+    std::vector<double> x, v, F;  // [dim][N]
     double diag[sce::kServeDiag];
     double self_w = 0.0, dt = 0.0;
     int64_t n_steps = 0;
+    int dim = 3;
 };
 
 // First-fit allocator over the arena, free blocks kept sorted by offset.
@@ -126,10 +127,10 @@ struct Mirrored {
     }
 };
 
-int64_t half_modes(int n)
+int64_t half_modes(int n, int dim)
 {
     const int64_t M = 2 * n + 1;
-    return (M * M * M - 1) / 2;
+    return dim == 2 ? (M * M - 1) / 2 : (M * M * M - 1) / 2;
 }
 
 double shape_host(int kind, double a, double kx, double ky, double kz)
@@ -180,7 +181,7 @@ struct sce_server_s {
     std::unordered_map<uint64_t, Result> done;
     std::deque<uint64_t> unpolled;
     // sum_H S^2/|k|^2 per (n_max, shape, a, L)
-    std::map<std::tuple<int, int, double, double>, double> self_cache;
+    std::map<std::tuple<int, int, double, double, int>, double> self_cache;
 
     // statistics
     std::vector<std::pair<double, int>> tick_lat;  // (seconds, resident requests)
@@ -214,14 +215,15 @@ sce_status shipfail(sce_server s, hipError_t e, const char *what)
         if (_e != hipSuccess) return shipfail(s, _e, #expr); \
     } while (0)
 
-double self_sum(sce_server s, int n, int kind, double a, double L)
+// sum over the stored modes of S^2 / |k|^2 (dim 2: the n_x = 0 slice)
+double self_sum(sce_server s, int n, int kind, double a, double L, int dim)
 {
-    const auto key = std::make_tuple(n, kind, a, L);
+    const auto key = std::make_tuple(n, kind, a, L, dim);
     auto it = s->self_cache.find(key);
     if (it != s->self_cache.end()) return it->second;
     const double f = 6.283185307179586476925286766559 / L;
     double sum = 0.0;
-    for (int nx = 0; nx <= n; ++nx)
+    for (int nx = 0; nx <= (dim == 2 ? 0 : n); ++nx)
         for (int ny = -n; ny <= n; ++ny)
             for (int nz = -n; nz <= n; ++nz) {
                 const bool inh = nx > 0 || (nx == 0 && (ny > 0 || (ny == 0 && nz > 0)));
@@ -397,9 +399,12 @@ void retire(sce_server s, const std::vector<Request *> &fin)
         const size_t N = (size_t)r->d.N;
         const double *h = s->stage.host + off;
         Result res;
-        res.x.assign(h, h + 3 * N);
-        res.v.assign(h + 3 * N, h + 6 * N);
-        res.F.assign(h + 6 * N, h + 9 * N);
+        // a two-dimensional request's vectors are the stored (y, z) components
+        const size_t o = r->d.dim == 2 ? N : 0;
+        res.dim = r->d.dim;
+        res.x.assign(h + o, h + 3 * N);
+        res.v.assign(h + 3 * N + o, h + 6 * N);
+        res.F.assign(h + 6 * N + o, h + 9 * N);
         std::memcpy(res.diag, h + 9 * N, sizeof(res.diag));
         res.self_w = r->self_w;
         res.dt = r->d.dt;
@@ -417,7 +422,7 @@ void retire(sce_server s, const std::vector<Request *> &fin)
     s->dirty = true;
 }
 
-void fill_diag(sce_diag *o, const double *d, double self_w, int64_t step, double dt)
+void fill_diag(sce_diag *o, const double *d, double self_w, int64_t step, double dt, int dim)
 {
     o->step = step;
     o->time = (double)step * dt;
@@ -426,9 +431,9 @@ void fill_diag(sce_diag *o, const double *d, double self_w, int64_t step, double
     o->field_self = self_w;
     o->interaction = d[2];
     o->total = d[0] + d[1];
-    o->momentum[0] = d[3];
-    o->momentum[1] = d[4];
-    o->momentum[2] = d[5];
+    o->momentum[0] = dim == 2 ? d[4] : d[3];
+    o->momentum[1] = dim == 2 ? d[5] : d[4];
+    o->momentum[2] = dim == 2 ? 0.0 : d[5];
     o->momentum_abs_sum = d[6];
     o->rho_abs_max = d[7];
 }
@@ -502,6 +507,8 @@ sce_status sce_server_submit(sce_server s, const sce_request *r, uint64_t *id)
     if (!std::isfinite(r->dt)) return sfail(s, SCE_EINVAL, "dt must be finite");
     if (r->N < 1 || r->N > ((int64_t)1 << 31)) return sfail(s, SCE_EINVAL, "N out of range");
     if (r->n_steps < 0) return sfail(s, SCE_EINVAL, "n_steps must be >= 0");
+    if (r->dim != 0 && r->dim != 2 && r->dim != 3) return sfail(s, SCE_EINVAL, "dim must be 2 or 3");
+    const int dim = r->dim == 2 ? 2 : 3;
     if (!r->x || !r->v || !r->q || !r->m) return sfail(s, SCE_EINVAL, "null particle array");
     for (int64_t j = 0; j < r->N; ++j)
         if (!(r->m[j] > 0.0)) return sfail(s, SCE_EINVAL, "masses must be > 0");
@@ -510,6 +517,7 @@ sce_status sce_server_submit(sce_server s, const sce_request *r, uint64_t *id)
     d.N = r->N;
     d.n = r->n_max;
     d.shape = r->shape_kind;
+    d.dim = dim;
     d.L = r->L;
     d.invL = 1.0 / r->L;
     d.a = r->a;
@@ -521,13 +529,22 @@ sce_status sce_server_submit(sce_server s, const sce_request *r, uint64_t *id)
     if (q->bytes > s->arena_bytes)
         return sfail(s, SCE_EINVAL, "request footprint exceeds the server's device budget");
     const size_t N = (size_t)r->N;
-    q->x.assign(r->x, r->x + 3 * N);
-    q->v.assign(r->v, r->v + 3 * N);
+    if (dim == 2) {
+        // stored as (0, x, y)
+        q->x.assign(3 * N, 0.0);
+        q->v.assign(3 * N, 0.0);
+        std::memcpy(q->x.data() + N, r->x, 2 * N * sizeof(double));
+        std::memcpy(q->v.data() + N, r->v, 2 * N * sizeof(double));
+    } else {
+        q->x.assign(r->x, r->x + 3 * N);
+        q->v.assign(r->v, r->v + 3 * N);
+    }
     q->q.assign(r->q, r->q + N);
     q->m.assign(r->m, r->m + N);
     double q2 = 0.0;
     for (size_t j = 0; j < N; ++j) q2 += r->q[j] * r->q[j];
-    q->self_w = q2 / (r->eps0 * r->L * r->L * r->L) * self_sum(s, r->n_max, r->shape_kind, r->a, r->L);
+    const double meas = dim == 2 ? r->L * r->L : r->L * r->L * r->L;
+    q->self_w = q2 / (r->eps0 * meas) * self_sum(s, r->n_max, r->shape_kind, r->a, r->L, dim);
     q->id = s->next_id++;
     q->t_submit = now_s();
     *id = q->id;
@@ -560,7 +577,7 @@ sce_status sce_server_tick(sce_server s, int32_t *n_active, int32_t *n_queued)
         double pr = 0.0;
         for (auto &r : s->active) {
             ++r->pass;
-            pr += (double)r->d.N * (double)half_modes(r->d.n);
+            pr += (double)r->d.N * (double)half_modes(r->d.n, r->d.dim);
             if (!r->x.empty()) {  // uploaded at admission; the copies have completed
                 std::vector<double>().swap(r->x);
                 std::vector<double>().swap(r->v);
@@ -603,8 +620,8 @@ sce_status sce_server_result(sce_server s, uint64_t id, double *x, double *v, do
     if (x) std::memcpy(x, r.x.data(), r.x.size() * sizeof(double));
     if (v) std::memcpy(v, r.v.data(), r.v.size() * sizeof(double));
     if (F) std::memcpy(F, r.F.data(), r.F.size() * sizeof(double));
-    if (first) fill_diag(first, r.diag, r.self_w, 0, r.dt);
-    if (last) fill_diag(last, r.diag + 8, r.self_w, r.n_steps, r.dt);
+    if (first) fill_diag(first, r.diag, r.self_w, 0, r.dt, r.dim);
+    if (last) fill_diag(last, r.diag + 8, r.self_w, r.n_steps, r.dt, r.dim);
     s->done.erase(it);
     return SCE_OK;
 }

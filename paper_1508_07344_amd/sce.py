@@ -50,7 +50,7 @@ class _Request(ctypes.Structure):
                 ("dt", ctypes.c_double), ("n_max", ctypes.c_int32), ("shape_kind", ctypes.c_int32),
                 ("N", ctypes.c_int64), ("n_steps", ctypes.c_int64),
                 ("x", ctypes.c_void_p), ("v", ctypes.c_void_p), ("q", ctypes.c_void_p),
-                ("m", ctypes.c_void_p)]
+                ("m", ctypes.c_void_p), ("dim", ctypes.c_int32)]
 
 
 class _ServerReport(ctypes.Structure):
@@ -415,11 +415,12 @@ class Server:
         q = np.ascontiguousarray(p.q, dtype=np.float64)
         m = np.ascontiguousarray(p.m, dtype=np.float64)
         steps = p.n_steps if n_steps is None else n_steps
+        dim = getattr(p, "dim", 3)
         r = _Request(p.L, p.a, p.eps0, p.dt, p.n_max, SHAPE[p.shape], p.N, steps,
-                     _host(x), _host(v), _host(q), _host(m))
+                     _host(x), _host(v), _host(q), _host(m), dim)
         rid = ctypes.c_uint64()
         self._chk(self._lib.sce_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)), "submit")
-        self._sizes[rid.value] = p.N
+        self._sizes[rid.value] = (p.N, dim)
         return rid.value
 
     def sce_server_tick(self):
@@ -437,8 +438,8 @@ class Server:
         """(x, v, F, first Diag, last Diag) of a finished request."""
         if rid not in self._sizes:
             raise SceError(SCE_EINVAL, f"result: unknown or already fetched request {rid}")
-        N = self._sizes[rid]
-        x, v, F = (np.empty((3, N)) for _ in range(3))
+        N, dim = self._sizes[rid]
+        x, v, F = (np.empty((dim, N)) for _ in range(3))
         d0, d1 = _Diag(), _Diag()
         self._chk(self._lib.sce_server_result(self._h, rid, _host(x), _host(v), _host(F),
                                               ctypes.byref(d0), ctypes.byref(d1)), "result")

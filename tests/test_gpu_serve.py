@@ -39,6 +39,10 @@ def _requests():
         ("n8", workloads.random_plasma(N=1025, n_max=8, a=0.05, salt=3), 2),
         ("plasma16", workloads.random_plasma(N=3001, n_max=16, a=0.02), 2),
         ("steps0", workloads.random_plasma(N=700, n_max=16, a=0.02, salt=5), 0),
+        # two-dimensional requests (line charges), resident in the same batches
+        ("kepler2d", workloads.kepler_2d(), 5),
+        ("thermal2d", workloads.thermal_2d(), 3),
+        ("plasma2d", workloads.random_plasma_2d(N=1500, n_max=12, a=0.03, salt=4), 2),
     ]
 
 
@@ -106,7 +110,10 @@ def test_batched_requests_match_oracle(prec, ref_runs):
             assert abs(d1.field - e1["field"]) <= tol * abs(e1["field"]), name
             assert abs(d1.kinetic - e1["kinetic"]) <= tol * max(e1["kinetic"], 1e-12), name
             assert abs(d1.total - (d1.kinetic + d1.field)) <= 1e-15 * abs(d1.total)
-            assert np.allclose(d1.momentum, e1["momentum"], rtol=0, atol=tol * e1["momentum_abs_sum"] + 1e-15)
+            assert x.shape == (p.dim, p.N) and F.shape == (p.dim, p.N)
+            assert np.allclose(d1.momentum[:p.dim], e1["momentum"], rtol=0,
+                               atol=tol * e1["momentum_abs_sum"] + 1e-15)
+            assert p.dim == 3 or d1.momentum[2] == 0.0
         st = srv.sce_server_stats()
         assert st["requests_done"] == len(ids)
         assert st["request_steps"] == sum(steps + 1 for _, (_, steps, _) in ref_runs.items())
@@ -158,7 +165,8 @@ def test_server_rejects_invalid_requests():
     p = workloads.random_plasma(N=100, n_max=8, a=0.05)
     with sce.Server(hbm_budget_bytes=1 << 20, precision="fp32") as srv:
         for bad in [p.with_(n_max=17), p.with_(n_max=0), p.with_(L=-1.0), p.with_(a=-0.1),
-                    p.with_(eps0=0.0), p.with_(dt=float("nan")), p.with_(m=np.zeros(100))]:
+                    p.with_(eps0=0.0), p.with_(dt=float("nan")), p.with_(m=np.zeros(100)),
+                    p.with_(dim=5)]:
             with pytest.raises(sce.SceError) as ei:
                 srv.sce_server_submit(bad)
             assert ei.value.status == sce.SCE_EINVAL
