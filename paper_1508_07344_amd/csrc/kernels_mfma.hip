@@ -120,29 +120,63 @@ __host__ __device__ inline int dep_rec_floats(int n)
     return (3 * (nb + 1) * 2 + 1 + 3) / 4 * 4;
 }
 
+// Inverse of feistel_perm: the same rounds undone in reverse order, walking
+// back into [0, N) the way the forward map walked out of it.
+__device__ inline uint32_t feistel_inv(uint32_t j, uint32_t N, int h)
+{
+    const uint32_t mask = h >= 16 ? 0xFFFFu : ((1u << h) - 1u);
+    uint32_t y = j;
+    do {
+        uint32_t L = y >> h, R = y & mask;
+#pragma unroll
+        for (int r = 3; r >= 0; --r) {
+            uint32_t f = L * 0x9E3779B1u + 0x7F4A7C15u * (uint32_t)(r + 1);
+            f ^= f >> 15;
+            f *= 0x85EBCA6Bu;
+            f ^= f >> 13;
+            const uint32_t pl = (R ^ f) & mask;
+            R = L;
+            L = pl;
+        }
+        y = (L << h) | R;
+    } while (y >= N);
+    return y;
+}
+
+// Thread j takes particle j (coalesced reads) and writes its record at its
+// place in the visiting order, feistel_inv(j), as 16-byte stores; NB anchor
+// blocks per axis, so the record sits in registers with static indices.
+template <int NB>
 __global__ void __launch_bounds__(256)
-k_deposit_prep(const double *__restrict__ pos, const double *__restrict__ q, int64_t N, int n,
+k_deposit_prep(const double *__restrict__ pos, const double *__restrict__ q, int64_t N,
                double invL, int h, double qfac, float *__restrict__ rec)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= N) return;
-    const int nb = (n + 1 + 7) / 8;
-    const int64_t j = feistel_perm((uint32_t)i, (uint32_t)N, h);
-    float *o = rec + i * dep_rec_floats(n);
+    constexpr int RF = (3 * (NB + 1) * 2 + 1 + 3) / 4 * 4;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= N) return;
+    const int64_t i = feistel_inv((uint32_t)j, (uint32_t)N, h);
+    float r[RF];
+#pragma unroll
+    for (int e = 0; e < RF; ++e) r[e] = 0.f;
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double t = frac(pos[d * N + j] * invL);
-        for (int blk = 0; blk < nb; ++blk) {
+#pragma unroll
+        for (int blk = 0; blk < NB; ++blk) {
             double c, sn;
             cis_turns(frac_mul(8 * blk, t), c, sn);
-            o[2 * (d * nb + blk)] = (float)c;
-            o[2 * (d * nb + blk) + 1] = (float)sn;
+            r[2 * (d * NB + blk)] = (float)c;
+            r[2 * (d * NB + blk) + 1] = (float)sn;
         }
         double c, sn;
         cis_turns(t, c, sn);
-        o[2 * (3 * nb + d)] = (float)c;
-        o[2 * (3 * nb + d) + 1] = (float)sn;
+        r[2 * (3 * NB + d)] = (float)c;
+        r[2 * (3 * NB + d) + 1] = (float)sn;
     }
-    o[6 * (nb + 1)] = (float)(q[j] * qfac);
+    r[6 * (NB + 1)] = (float)(q[j] * qfac);
+    float4 *o = reinterpret_cast<float4 *>(rec + i * RF);
+#pragma unroll
+    for (int e = 0; e < RF / 4; ++e) o[e] = make_float4(r[4 * e], r[4 * e + 1], r[4 * e + 2], r[4 * e + 3]);
 }
 
 // LDS table layouts of the deposit.  Row strides are those of the largest
@@ -613,8 +647,20 @@ hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q
                                const Geom &g, double L, const MfmaDepositPlan &pl, double qscale,
                                float *rec, double *part)
 {
-    hipLaunchKernelGGL(k_deposit_prep, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, pos, q,
-                       N, g.n, 1.0 / L, (int)pl.perm, (double)kDepOpScale / qscale, rec);
+    const dim3 pg((unsigned)((N + 255) / 256));
+    const double qf = (double)kDepOpScale / qscale;
+    const int hp = (int)pl.perm;
+    switch ((g.n + 1 + 7) / 8) {
+    case 1: hipLaunchKernelGGL(k_deposit_prep<1>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
+    case 2: hipLaunchKernelGGL(k_deposit_prep<2>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
+    case 3: hipLaunchKernelGGL(k_deposit_prep<3>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
+    case 4: hipLaunchKernelGGL(k_deposit_prep<4>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
+    case 5: hipLaunchKernelGGL(k_deposit_prep<5>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
+    case 6: hipLaunchKernelGGL(k_deposit_prep<6>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
+    case 7: hipLaunchKernelGGL(k_deposit_prep<7>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
+    case 8: hipLaunchKernelGGL(k_deposit_prep<8>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
+    default: hipLaunchKernelGGL(k_deposit_prep<9>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
+    }
     // H carries q / qscale scaled by 7/8, the CS operand another 7/8
     const double unscale_dc = qscale / (double)kDepOpScale;
     const double unscale_mf = unscale_dc / (double)kDepOpScale;
