@@ -66,32 +66,13 @@ __device__ inline f32x4 mfma_split(half8 ah, half8 al, half8 bh, half8 bl, f32x4
     return mfma16(ah, bh, acc);
 }
 
-// Pseudo-random bijection of [0, N): a 4-round Feistel network on 2h bits
-// (2^(2h) >= N) with cycle-walking back into [0, N).  The deposit visits the
-// particles of a split in this order so that each split is an unstructured
-// sample of the particles: its FP32 sums then grow like random walks for every
-// mode, whatever the input order (an affine order i*A mod N is a rank-1
-// lattice and stays coherent for some wave vectors).
-__device__ inline uint32_t feistel_perm(uint32_t i, uint32_t N, int h)
-{
-    const uint32_t mask = h >= 16 ? 0xFFFFu : ((1u << h) - 1u);
-    uint32_t x = i;
-    do {
-        uint32_t L = x >> h, R = x & mask;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            uint32_t f = R * 0x9E3779B1u + 0x7F4A7C15u * (uint32_t)(r + 1);
-            f ^= f >> 15;
-            f *= 0x85EBCA6Bu;
-            f ^= f >> 13;
-            const uint32_t nl = R;
-            R = (L ^ f) & mask;
-            L = nl;
-        }
-        x = (L << h) | R;
-    } while (x >= N);
-    return x;
-}
+// The deposit visits the particles of a split in a pseudo-random order, so
+// that each split is an unstructured sample of the particles: its FP32 sums
+// then grow like random walks for every mode, whatever the input order (an
+// affine order i*A mod N is a rank-1 lattice and stays coherent for some wave
+// vectors).  The order is a bijection of [0, N): a 4-round Feistel network on
+// 2h bits (2^(2h) >= N), each round (L, R) -> (R, L ^ f_r(R)), with cycle
+// walking back into [0, N).  Particle j's record goes to slot feistel_inv(j).
 
 // ------------------------------------------------------------------ deposit
 // Particles are taken in chunks of 32 (the K depth of one matrix instruction).
@@ -120,8 +101,8 @@ __host__ __device__ inline int dep_rec_floats(int n)
     return (3 * (nb + 1) * 2 + 1 + 3) / 4 * 4;
 }
 
-// Inverse of feistel_perm: the same rounds undone in reverse order, walking
-// back into [0, N) the way the forward map walked out of it.
+// Inverse of the visiting-order map: its rounds undone in reverse order,
+// walking back into [0, N) the way the forward map walks out of it.
 __device__ inline uint32_t feistel_inv(uint32_t j, uint32_t N, int h)
 {
     const uint32_t mask = h >= 16 ? 0xFFFFu : ((1u << h) - 1u);
