@@ -131,6 +131,19 @@ sce_status hipfail(sce_ctx c, hipError_t e, const char *what)
         if (_e != hipSuccess) return hipfail(c, _e, #expr); \
     } while (0)
 
+// Device allocations sized by the caller's input: running out of memory is
+// SCE_ENOMEM and leaves the context usable (the error is cleared); any other
+// failure is a device error.
+#define ALLOCCHK(c, expr)                                                               \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e == hipErrorOutOfMemory) {                                                \
+            (void)hipGetLastError();                                                    \
+            return fail(c, SCE_ENOMEM, std::string(#expr) + ": out of device memory");  \
+        }                                                                               \
+        if (_e != hipSuccess) return hipfail(c, _e, #expr);                             \
+    } while (0)
+
 Geom make_geom(int n, int dim)
 {
     Geom g;
@@ -421,6 +434,10 @@ sce_status ensure_particle_buffers(sce_ctx c, int64_t N)
 {
     if (N <= c->cap) return SCE_OK;
     c->gen++;
+    // no particles until every buffer of the new size exists
+    c->N = 0;
+    c->cap = 0;
+    c->fields_valid = c->force_valid = c->phi_valid = false;
     free_devp(c->pos);
     free_devp(c->vel);
     free_devp(c->q);
@@ -432,17 +449,17 @@ sce_status ensure_particle_buffers(sce_ctx c, int64_t N)
     free_devp(c->Fk);
     free_devp(c->Pk);
     if (c->field == SCE_FIELD_TENT) {
-        HIPCHK(c, dev_alloc(c->qw, N * sizeof(double)));
-        HIPCHK(c, dev_alloc(c->env, 4 * N * sizeof(double)));
-        HIPCHK(c, dev_alloc(c->Fk, 3 * N * sizeof(double)));
-        HIPCHK(c, dev_alloc(c->Pk, N * sizeof(double)));
+        ALLOCCHK(c, dev_alloc(c->qw, N * sizeof(double)));
+        ALLOCCHK(c, dev_alloc(c->env, 4 * N * sizeof(double)));
+        ALLOCCHK(c, dev_alloc(c->Fk, 3 * N * sizeof(double)));
+        ALLOCCHK(c, dev_alloc(c->Pk, N * sizeof(double)));
     }
-    HIPCHK(c, dev_alloc(c->pos, 3 * N * sizeof(double)));
-    HIPCHK(c, dev_alloc(c->vel, 3 * N * sizeof(double)));
-    HIPCHK(c, dev_alloc(c->q, N * sizeof(double)));
-    HIPCHK(c, dev_alloc(c->m, N * sizeof(double)));
-    HIPCHK(c, dev_alloc(c->F, 3 * N * sizeof(double)));
-    HIPCHK(c, dev_alloc(c->phi, N * sizeof(double)));
+    ALLOCCHK(c, dev_alloc(c->pos, 3 * N * sizeof(double)));
+    ALLOCCHK(c, dev_alloc(c->vel, 3 * N * sizeof(double)));
+    ALLOCCHK(c, dev_alloc(c->q, N * sizeof(double)));
+    ALLOCCHK(c, dev_alloc(c->m, N * sizeof(double)));
+    ALLOCCHK(c, dev_alloc(c->F, 3 * N * sizeof(double)));
+    ALLOCCHK(c, dev_alloc(c->phi, N * sizeof(double)));
     c->cap = N;
     return SCE_OK;
 }
@@ -453,7 +470,7 @@ sce_status ensure_bytes(sce_ctx c, void *&p, size_t &have, size_t need)
     c->gen++;
     free_dev(p);
     have = 0;
-    HIPCHK(c, hipMalloc(&p, need));
+    ALLOCCHK(c, hipMalloc(&p, need));
     have = need;
     return SCE_OK;
 }

@@ -312,3 +312,26 @@ def _k1_index(n):
     """Canonical index of mode (1, 0, 0): after the n_x = 0 block (n + n(2n+1)
     modes) and the n_y = -n..-1 rows of n_x = 1, at n_z = 0."""
     return n + n * (2 * n + 1) + n * (2 * n + 1) + n
+
+
+def test_out_of_device_memory_leaves_the_context_usable():
+    """A particle count beyond device memory is SCE_ENOMEM before any array is
+    read; the context then holds no particles, and takes a normal set again."""
+    import ctypes
+    sce = _gpu()
+    p = workloads.random_plasma(N=500, n_max=6, a=0.05, salt=9)
+    ref = oracle.fields(p.positions(), p.q, p.L, p.n_max, p.shape, p.a, p.eps0)
+    with sce.Context.from_particles(p, precision="fp64") as c:
+        lib = sce.load_library()
+        tiny = np.zeros(3)
+        h = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        st = lib.sce_set_particles(c._h, 1 << 36, h(tiny), h(tiny), h(tiny), h(tiny), 0)
+        assert st == sce.SCE_ENOMEM
+        assert "memory" in lib.sce_last_error(c._h).decode()
+        with pytest.raises(sce.SceError) as ei:
+            c.sce_force()
+        assert ei.value.status == sce.SCE_ESTATE  # no particles
+        c.sce_set_particles(p.positions(), p.velocities(), p.q, p.m)
+        F = c.sce_force()
+        c.sce_step(p.dt, 3)
+    assert e_F(F, ref.F) <= TOL["fp64"]
