@@ -627,25 +627,91 @@ k_force(const double *__restrict__ pos, const double *__restrict__ q,
 }
 
 // Medium particle counts (too few blocks of 256 particles to fill the compute
-// units): blockIdx.y takes the n_x lines [y L / S, (y + 1) L / S) of L lines,
-// S = gridDim.y, and writes its raw sums to part[y][4][N] (fx, fy, fz, ph);
-// k_force_combine adds the S line groups in order, scales and kicks.
+// units): blockIdx.y takes the rows [y R / S, (y + 1) R / S), S = gridDim.y,
+// and writes its raw sums to part[y][4][N] (fx, fy, fz, ph); k_force_combine
+// adds the S row groups in order, scales and kicks.  A group's rows are whole
+// n_x lines except possibly its first and last (clipped in n_y); the row phase
+// is anchored with its own FP64 exponential at the start of each line and
+// follows the recurrence along n_y, as in the one-particle-per-lane kernel.
+// FP64: four waves per SIMD, since the grid is sized for one round of four
+// blocks per compute unit and at 129 registers the kernel would need two.
 template <typename T, int NZC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 1)))
 k_force_lines(const double *__restrict__ pos, const T *__restrict__ ftab,
-              const T *__restrict__ psi0, int n, int lines, int nzp, double invL, int64_t N,
+              const T *__restrict__ psi0, int n, int R, int nzp, double invL, int64_t N,
               double *__restrict__ part)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t jc = j < N ? j : N - 1;
     const int S = gridDim.y, y = blockIdx.y;
-    const int l0 = y * lines / S, l1 = (y + 1) * lines / S;
-    const int r0 = l0 == 0 ? 0 : (n + 1) + (l0 - 1) * (2 * n + 1);
+    const int r0 = (int)((int64_t)y * R / S), r1 = (int)((int64_t)(y + 1) * R / S);
     const double tx = frac(pos[jc] * invL);
     const double ty = frac(pos[N + jc] * invL);
     const double tz = frac(pos[2 * N + jc] * invL);
+    double eyc, eys;
+    cis_turns(ty, eyc, eys);
+    double ezc, ezs;
+    cis_turns(tz, ezc, ezs);
     double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
-    force_line_sums<T, NZC>(ftab, psi0, n, nzp, l0, l1, r0, tx, ty, tz, fx, fy, fz, ph);
+    for (int c0 = 0; c0 < nzp; c0 += NZC) {
+        T cz[NZC], sz[NZC];
+        {
+            double c, s;
+#pragma unroll
+            for (int k = 0; k < NZC; ++k) {
+                if ((k & 7) == 0) {
+                    cis_turns(frac_mul(c0 + 1 + k, tz), c, s);
+                } else {
+                    const double cn = c * ezc - s * ezs;
+                    s = s * ezc + c * ezs;
+                    c = cn;
+                }
+                cz[k] = (T)c;
+                sz[k] = (T)s;
+            }
+        }
+        // rows r0 .. r1-1: lines l0 .. l1, the first from n_y = ys, the last to n_y = ye
+        int l0, ys, l1, ye;
+        row_nxny(r0, n, l0, ys);
+        row_nxny(r1 - 1, n, l1, ye);
+        int r = r0;
+        for (int nx = l0; nx <= l1; ++nx) {
+            const int ny0 = nx == l0 ? ys : (nx == 0 ? 0 : -n);
+            const int ny1 = nx == l1 ? ye : n;
+            double hc, hs;
+            cis_turns(frac_lin(nx, tx, ny0, ty), hc, hs);
+            for (int ny = ny0; ny <= ny1; ++ny, ++r) {
+                const T *ft = ftab + ((int64_t)r * nzp + c0) * 8;
+                T u0r = (T)0, u0i = (T)0, u1r = (T)0, u1i = (T)0;
+                if (c0 == 0) {
+                    u0r = psi0[2 * r];
+                    u0i = psi0[2 * r + 1];
+                }
+#pragma unroll
+                for (int k = 0; k < NZC; ++k) {
+                    const T c = cz[k], s = sz[k];
+                    u0r = fma(ft[8 * k + 0], c, u0r);
+                    u0i = fma(ft[8 * k + 1], c, u0i);
+                    u0r = fma(-ft[8 * k + 3], s, u0r);
+                    u0i = fma(ft[8 * k + 2], s, u0i);
+                    u1r = fma(ft[8 * k + 4], c, u1r);
+                    u1i = fma(ft[8 * k + 5], c, u1i);
+                    u1r = fma(-ft[8 * k + 7], s, u1r);
+                    u1i = fma(ft[8 * k + 6], s, u1i);
+                }
+                const double im0 = hc * (double)u0i + hs * (double)u0r;
+                const double re0 = hc * (double)u0r - hs * (double)u0i;
+                const double im1 = hc * (double)u1i + hs * (double)u1r;
+                fx = fma((double)nx, im0, fx);
+                fy = fma((double)ny, im0, fy);
+                fz += im1;
+                ph += re0;
+                const double t = hc * eyc - hs * eys;
+                hs = hs * eyc + hc * eys;
+                hc = t;
+            }
+        }
+    }
     if (j < N) {
         double *o = part + (int64_t)y * 4 * N + j;
         o[0] = fx;
@@ -802,9 +868,9 @@ int force_line_groups(const Geom &g, int64_t N, int elem_bytes)
 {
     if (N <= (elem_bytes == 8 ? force_small_max<double>() : force_small_max<float>())) return 1;
     const int64_t blocks = (N + 255) / 256;
-    if (blocks >= kForceLineBlocks || g.lines < 2) return 1;
+    if (blocks >= kForceLineBlocks) return 1;
     const int64_t want = (kForceLineBlocks + blocks - 1) / blocks;
-    return (int)(want < g.lines ? want : g.lines);
+    return (int)(want < g.R / 8 ? want : g.R / 8);  // at least 8 rows per group
 }
 
 template <typename T, int NZC>
@@ -814,7 +880,7 @@ hipError_t launch_force_lines(hipStream_t s, const double *pos, const double *q,
 {
     const int64_t blocks = (N + 255) / 256;
     hipLaunchKernelGGL((k_force_lines<T, NZC>), dim3((unsigned)blocks, (unsigned)S), dim3(256), 0, s, pos,
-                       ftab, psi0, g.n, g.lines, g.nzp, 1.0 / L, N, part);
+                       ftab, psi0, g.n, g.R, g.nzp, 1.0 / L, N, part);
     hipLaunchKernelGGL(k_force_combine, dim3((unsigned)blocks), dim3(256), 0, s, part, S, q, m, vel, N,
                        1.0 / L, kick, F, phi);
     return hipGetLastError();

@@ -97,7 +97,7 @@ hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, co
 
 // Force (and potential) at the current positions; optional kick v += kick F/m.
 // Between the small-count kernel and kForceLineBlocks blocks of 256 particles
-// the n_x lines are split over force_line_groups(...) groups of blocks, whose
+// the rows are split evenly over force_line_groups(...) groups of blocks, whose
 // FP64 partial sums go to part ([groups][4][N] doubles, caller-owned) and are
 // then added in a fixed order.
 constexpr int kForceLineBlocks = 1024;
