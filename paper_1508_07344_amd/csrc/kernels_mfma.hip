@@ -442,9 +442,11 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
         const int b = (int)(c & 1);
         const float2 *ta = tab_a(b), *tb = tab_b(b);
         const _Float16 *chi = cs_hi(b), *clo = cs_lo(b);
+        // H fragments of every row tile first, then each CS tile read once
+        // and multiplied with all of them
+        half8 bre_h[NTW], bre_l[NTW], bim_h[NTW], bim_l[NTW];
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt) {
-            half8 bre_h, bre_l, bim_h, bim_l;
             float sre = 0.f, sim = 0.f;
             // one 8-byte read per table entry: the compiler would otherwise pair
             // the reads of two particles into one two-address read, whose halves
@@ -469,23 +471,26 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                 const half2_t mh = __builtin_convertvector(hm, half2_t);
                 const half2_t rl = split_lo2(hr, rh);
                 const half2_t ml = split_lo2(hm, mh);
-                bre_h[i] = rh[0];
-                bre_h[i + 1] = rh[1];
-                bre_l[i] = rl[0];
-                bre_l[i + 1] = rl[1];
-                bim_h[i] = mh[0];
-                bim_h[i + 1] = mh[1];
-                bim_l[i] = ml[0];
-                bim_l[i + 1] = ml[1];
+                bre_h[nt][i] = rh[0];
+                bre_h[nt][i + 1] = rh[1];
+                bre_l[nt][i] = rl[0];
+                bre_l[nt][i + 1] = rl[1];
+                bim_h[nt][i] = mh[0];
+                bim_h[nt][i + 1] = mh[1];
+                bim_l[nt][i] = ml[0];
+                bim_l[nt][i + 1] = ml[1];
             }
             dc[nt][0] += sre;
             dc[nt][1] += sim;
+        }
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                const half8 ah = *reinterpret_cast<const half8 *>(&chi[(mt * 64 + lane) * 8]);
-                const half8 al = *reinterpret_cast<const half8 *>(&clo[(mt * 64 + lane) * 8]);
-                acc[mt][nt][0] = mfma_split(ah, al, bre_h, bre_l, acc[mt][nt][0]);
-                acc[mt][nt][1] = mfma_split(ah, al, bim_h, bim_l, acc[mt][nt][1]);
+        for (int mt = 0; mt < MT; ++mt) {
+            const half8 ah = *reinterpret_cast<const half8 *>(&chi[(mt * 64 + lane) * 8]);
+            const half8 al = *reinterpret_cast<const half8 *>(&clo[(mt * 64 + lane) * 8]);
+#pragma unroll
+            for (int nt = 0; nt < NTW; ++nt) {
+                acc[mt][nt][0] = mfma_split(ah, al, bre_h[nt], bre_l[nt], acc[mt][nt][0]);
+                acc[mt][nt][1] = mfma_split(ah, al, bim_h[nt], bim_l[nt], acc[mt][nt][1]);
             }
         }
         if ((c & ((1 << kDepDcLog) - 1)) == ((1 << kDepDcLog) - 1)) {
@@ -858,8 +863,12 @@ __device__ inline void stage_w(const half8 *__restrict__ src, half8 *dst, int np
             (__attribute__((address_space(3))) void *)(dst + 64 * p), 16, 0, 0);
 }
 
+// For KS <= 2 the launch bound asks for 4 waves per SIMD (two blocks per CU):
+// without it the variant that also sums the potential takes 132 VGPRs at
+// KS = 2 and runs 3 waves per SIMD; with it the compiler schedules it into 126
+// without spills.  KS = 3, 4 need more than 128 VGPRs and run 2 waves per SIMD.
 template <int KS, bool PHI>
-__global__ void __launch_bounds__(64 * kForceWaves, 2)
+__global__ void __launch_bounds__(64 * kForceWaves, KS <= 2 ? 4 : 2)
 k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
              const double *__restrict__ m, double *__restrict__ vel, const _Float16 *__restrict__ wf,
              const float4 *__restrict__ rinfo, int n, int lines, double invL, int64_t N, double kick,
