@@ -664,28 +664,32 @@ hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q
 }
 
 // ------------------------------------------------------------------ force table pack
-// The force visits rows in quads of 4 (one row per lane group).  Every n_x
-// line is padded to whole quads so that no quad mixes two lines: line 0
-// (n_x = 0, n_y = 0..n) has q0 quads, lines n_x = 1..lines-1 have qL quads
-// each (lines = n + 1; a two-dimensional context has line 0 only), and
-// the row arrays are padded further to a multiple of kForceQuadAlign quads
-// (whole LDS stages of the force kernel).
-// Padding rows carry zero weights.
-constexpr int kForceQuadAlign = 16;
+// The force visits rows in quads of 4 (one row per lane group), in runs that
+// hold one coordinate fixed, so that a lane's row phase advances by the same
+// step at every quad of a run: first line 0 (n_x = 0, n_y = 0..n, q0 quads,
+// n_y of lane group i = 4 t + i), then, in a three-dimensional context, one
+// column per n_y = -n..n with n_x = 1..n (qC quads each, n_x of lane group i
+// = 4 t' + i + 1).  Runs are padded to whole quads (a column needs no padding
+// when 4 divides n), and the row arrays further to a multiple of
+// kForceQuadAlign quads (whole LDS stages of the force kernel).  Padding rows
+// carry zero weights.
+constexpr int kForceQuadAlign = 8;
 // quads per LDS stage of the force kernel for KS K steps of 32
 template <int KS>
 constexpr int force_tm() { return 8; }
 
 struct ForceQuads {
-    int q0, qL, Q, Qpad;
+    int q0, qC, Q, Qpad;  // quads of line 0, per column, in all
 };
 
+// lines = n + 1 in three dimensions (line 0 and 2n + 1 columns), 1 in two
+// (line 0 only)
 __host__ __device__ inline ForceQuads force_quads(int n, int lines)
 {
     ForceQuads f;
     f.q0 = (n + 1 + 3) / 4;
-    f.qL = (2 * n + 1 + 3) / 4;
-    f.Q = f.q0 + (lines - 1) * f.qL;
+    f.qC = (n + 3) / 4;
+    f.Q = f.q0 + (lines > 1 ? (2 * n + 1) * f.qC : 0);
     f.Qpad = (f.Q + kForceQuadAlign - 1) / kForceQuadAlign * kForceQuadAlign;
     return f;
 }
@@ -701,10 +705,10 @@ __host__ __device__ inline int force_row(int pr, int n, const ForceQuads &f, int
         ny = 4 * t + i;
         return ny <= n ? ny : -1;
     }
-    const int l = (t - f.q0) / f.qL, pos = 4 * ((t - f.q0) - l * f.qL) + i;
-    nx = l + 1;
-    ny = pos - n;
-    return pos < 2 * n + 1 ? (n + 1) + l * (2 * n + 1) + pos : -1;
+    const int c = (t - f.q0) / f.qC;
+    nx = 4 * ((t - f.q0) - c * f.qC) + i + 1;
+    ny = c - n;
+    return nx <= n ? (n + 1) + (nx - 1) * (2 * n + 1) + c : -1;
 }
 
 // Per padded row, two records of four floats:
@@ -841,13 +845,15 @@ hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0
 // (U0, U1) / s, and
 //   Im(g U0) / s, Im(g U1) / s       4
 //   F += (n_x s, n_y s, s) (...)     3   (record B)
-//   g <- g cis(4 theta_y)            4
-// where g = exp(2 pi i (n_x t_x + n_y t_y)) is the lane's row phase in FP32.
-// Quads never cross lines, so the step is the same for every lane.  At each
-// line end the FP32 sums go into FP64 and g restarts from the next line's
-// phase, kept by an FP64 complex recurrence in t_x (exact to ~1e-15 over all
-// lines), so FP32 phase steps never run longer than one line.  PHI: also sum
-// the potential (only the diagnostics need it).
+//   g <- g e4                        4
+// where g = exp(2 pi i (n_x t_x + n_y t_y)) is the lane's row phase in FP32
+// and e4 = cis(4 theta_y) along line 0, cis(4 theta_x) along the columns (the
+// lane's copy waits in LDS until line 0 ends).  Quads never cross runs, so the
+// step is the same for every lane.  At each run end the FP32 sums go into
+// FP64 and g restarts from the next column's phase, kept by an FP64 complex
+// recurrence in t_y (exact to ~1e-15 over all columns), so FP32 phase steps
+// never run longer than one run.  PHI: also sum the potential (the
+// diagnostics and finite-width field shapes need it).
 constexpr int kForceWaves = 8;
 constexpr int kForceNT = 2;
 constexpr int kForceBlockParticles = kForceWaves * kForceNT * 16;
@@ -882,6 +888,7 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
     constexpr int PIECES = kForceTM * KS * 2;          // 1 KB W pieces per stage
     constexpr int STAGE = PIECES * 64 + 8 * kForceTM;  // half8 per stage buffer (W, records A, B)
     __shared__ half8 wbuf0[STAGE], wbuf1[STAGE];
+    __shared__ float2 e4x[NT][64 * kForceWaves];  // each lane's cis(4 theta_x)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -910,7 +917,7 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
 
     half8 bh[NT][KS], bl[NT][KS];
     float gc[NT], gs[NT], e4c[NT], e4s[NT];
-    double lc[NT], ls[NT], stc[NT], sts[NT];  // next line's phase; step cis(t_x)
+    double lc[NT], ls[NT], stc[NT], sts[NT];  // next column's phase; step cis(t_y)
     double fx[NT], fy[NT], fz[NT], fp[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
@@ -944,18 +951,20 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
         cis_turns(frac_mul(4, ty), a, b);
         e4c[nt] = (float)a;
         e4s[nt] = (float)b;
-        // line 0 starts at n_y = g; line 1 at (n_x, n_y) = (1, g - n)
+        cis_turns(frac_mul(4, tx), a, b);
+        e4x[nt][tid] = make_float2((float)a, (float)b);
+        // line 0 starts at n_y = g; the first column at (n_x, n_y) = (g + 1, -n)
         cis_turns(frac_mul(g, ty), a, b);
         gc[nt] = (float)a;
         gs[nt] = (float)b;
-        cis_turns(frac_lin(1, tx, g - n, ty), lc[nt], ls[nt]);
-        cis_turns(tx, stc[nt], sts[nt]);
+        cis_turns(frac_lin(g + 1, tx, -n, ty), lc[nt], ls[nt]);
+        cis_turns(ty, stc[nt], sts[nt]);
         fx[nt] = fy[nt] = fz[nt] = fp[nt] = 0.0;
     }
     float sx[NT], sy[NT], sz[NT], sp[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) sx[nt] = sy[nt] = sz[nt] = sp[nt] = 0.f;
-    int next_line = fq.q0;  // first quad of the next line
+    int next_run = fq.q0;  // first quad of the next run
 
     auto products = [&](const half8 *wl, int tt, f32x4 (&acc)[NT]) {
         half8 ah[KS], al[KS];
@@ -986,9 +995,17 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
             gs[nt] = gs[nt] * e4c[nt] + gc[nt] * e4s[nt];
             gc[nt] = c;
         }
-        if (t + 1 == next_line) {
-            // end of a line: FP32 sums into FP64, phase of the next line's first row
-            next_line += fq.qL;
+        if (t + 1 == next_run) {
+            // end of a run: FP32 sums into FP64, phase of the next column's first row
+            if (t + 1 == fq.q0) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const float2 e = e4x[nt][tid];
+                    e4c[nt] = e.x;
+                    e4s[nt] = e.y;
+                }
+            }
+            next_run += fq.qC;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 fx[nt] += (double)sx[nt];
