@@ -173,7 +173,9 @@ sce_status sce_set_options(sce_ctx ctx, double eps0, int32_t precision, int32_t 
 /* Copy N particles into the context.  x, v: [3][N]; q, m: [N] (m > 0).
  * Positions outside [0, L) are accepted and wrapped (kept as given in a
  * tent-field context).  Resets the step counter
- * and the cached force.  SCE_EINVAL if N < 1 or a pointer is NULL. */
+ * and the cached force.  SCE_EINVAL if N < 1, N >= 2^32 or a pointer is
+ * NULL; SCE_ENOMEM if the particle arrays do not fit in device memory (the
+ * context then holds no particles). */
 sce_status sce_set_particles(sce_ctx ctx, int64_t N, const double *x, const double *v,
                              const double *q, const double *m, int32_t on_device);
 

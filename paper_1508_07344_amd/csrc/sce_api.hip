@@ -819,6 +819,9 @@ sce_status sce_set_particles(sce_ctx c, int64_t N, const double *x, const double
     sce_status st = check_ready(c);
     if (st) return st;
     if (N < 1) return fail(c, SCE_EINVAL, "N must be >= 1");
+    // the deposit's visiting order is a permutation of 32-bit indices (and
+    // 2^32 particles would not fit in device memory anyway)
+    if (N > (int64_t)0xFFFFFFFF) return fail(c, SCE_EINVAL, "N must be below 2^32");
     if (!x || !v || !q || !m) return fail(c, SCE_EINVAL, "NULL particle array");
     st = ensure_particle_buffers(c, N);
     if (st) return st;

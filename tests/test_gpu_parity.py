@@ -326,6 +326,10 @@ def test_out_of_device_memory_leaves_the_context_usable():
         tiny = np.zeros(3)
         h = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         st = lib.sce_set_particles(c._h, 1 << 36, h(tiny), h(tiny), h(tiny), h(tiny), 0)
+        assert st == sce.SCE_EINVAL  # beyond the 32-bit particle index
+        assert "2^32" in lib.sce_last_error(c._h).decode()
+        # 2^32 - 1 particles need over 370 GB of particle arrays
+        st = lib.sce_set_particles(c._h, (1 << 32) - 1, h(tiny), h(tiny), h(tiny), h(tiny), 0)
         assert st == sce.SCE_ENOMEM
         assert "memory" in lib.sce_last_error(c._h).decode()
         with pytest.raises(sce.SceError) as ei:
