@@ -404,9 +404,9 @@ __device__ inline double block_max(double v, double *sh)
 // (37 blocks) while the loop streamed the partials.
 constexpr int kReduceWays = 8;
 
-template <typename T>
+template <typename T, typename P>
 __global__ void __launch_bounds__(64 * kReduceWays)
-k_reduce_solve(const double *__restrict__ part, int splits, int n, int R, int Rpad, int nzp,
+k_reduce_solve(const P *__restrict__ part, int splits, int n, int R, int Rpad, int nzp,
                const double *__restrict__ Stab, const double *__restrict__ Gtab,
                const double *__restrict__ Ktab, double2 *__restrict__ rho,
                double2 *__restrict__ psi, T *__restrict__ ftab, T *__restrict__ psi0,
@@ -423,12 +423,12 @@ k_reduce_solve(const double *__restrict__ part, int splits, int n, int R, int Rp
             const int nz = (int)(cell / R);
             const int row = (int)(cell - (int64_t)nz * R);
             const int64_t sstride = (int64_t)n1 * 4 * Rpad;
-            const double *pp = part + (int64_t)way * sstride + (int64_t)nz * 4 * Rpad + row;
+            const P *pp = part + (int64_t)way * sstride + (int64_t)nz * 4 * Rpad + row;
             for (int sp = way; sp < splits; sp += kReduceWays, pp += kReduceWays * sstride) {
-                Pr += pp[0];
-                Pi += pp[Rpad];
-                Qr += pp[2 * (int64_t)Rpad];
-                Qi += pp[3 * (int64_t)Rpad];
+                Pr += (double)pp[0];
+                Pi += (double)pp[Rpad];
+                Qr += (double)pp[2 * (int64_t)Rpad];
+                Qi += (double)pp[3 * (int64_t)Rpad];
             }
         }
         ways[way][lane] = make_double4(Pr, Pi, Qr, Qi);
@@ -499,8 +499,8 @@ k_reduce_solve(const double *__restrict__ part, int splits, int n, int R, int Rp
     }
 }
 
-template <typename T>
-hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, const Geom &g,
+template <typename T, typename P>
+hipError_t launch_reduce_solve(hipStream_t s, const P *part, int splits, const Geom &g,
                                const double *Stab, const double *Gtab, const double *Ktab,
                                double2 *rho, double2 *psi, T *ftab, T *psi0, double *wpart,
                                int *wblocks)
@@ -508,7 +508,7 @@ hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, co
     const int64_t cells = (int64_t)(g.n + 1) * g.R;
     const int blocks = (int)((cells + 63) / 64);
     *wblocks = blocks;
-    hipLaunchKernelGGL(k_reduce_solve<T>, dim3(blocks), dim3(64 * kReduceWays), 0, s, part, splits, g.n, g.R,
+    hipLaunchKernelGGL((k_reduce_solve<T, P>), dim3(blocks), dim3(64 * kReduceWays), 0, s, part, splits, g.n, g.R,
                        g.Rpad, g.nzp, Stab, Gtab, Ktab, rho, psi, ftab, psi0, wpart);
     return hipGetLastError();
 }
@@ -1034,8 +1034,9 @@ template hipError_t launch_phase_table<float>(hipStream_t, const double *, int64
 template hipError_t launch_phase_table<double>(hipStream_t, const double *, int64_t, const Geom &, double, double2 *, double *);
 template hipError_t launch_deposit<float>(hipStream_t, const double2 *, const float *, const double *, int64_t, const Geom &, const DepositPlan &, double *);
 template hipError_t launch_deposit<double>(hipStream_t, const double2 *, const double *, const double *, int64_t, const Geom &, const DepositPlan &, double *);
-template hipError_t launch_reduce_solve<float>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, float *, float *, double *, int *);
-template hipError_t launch_reduce_solve<double>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, double *, double *, double *, int *);
+template hipError_t launch_reduce_solve<float, double>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, float *, float *, double *, int *);
+template hipError_t launch_reduce_solve<double, double>(hipStream_t, const double *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, double *, double *, double *, int *);
+template hipError_t launch_reduce_solve<float, float>(hipStream_t, const float *, int, const Geom &, const double *, const double *, const double *, double2 *, double2 *, float *, float *, double *, int *);
 template hipError_t launch_force<float>(hipStream_t, const double *, const double *, const double *, double *, const float *, const float *, const Geom &, double, int64_t, double, double *, double *, double *);
 template hipError_t launch_force<double>(hipStream_t, const double *, const double *, const double *, double *, const double *, const double *, const Geom &, double, int64_t, double, double *, double *, double *);
 

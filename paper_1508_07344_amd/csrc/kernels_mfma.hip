@@ -244,7 +244,7 @@ template <int MT>
 __global__ void __launch_bounds__(kDepThreads)
 k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                int64_t per_split, int row_blocks, int splits, double unscale_mf, double unscale_dc,
-               double *__restrict__ part)
+               float *__restrict__ part)
 {
     const int blk_l = blockIdx.x;
     const int blk_t = blk_l / kXcds;
@@ -518,7 +518,8 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     const int64_t last = nchunks - 1;
     const double fsign = last >= 0 && ((last >> kDepFlipLog) & 1) ? -1.0 : 1.0;
     const double outscale = unscale_mf * fsign;
-    double *pb = part + (int64_t)split * (int64_t)n1 * 4 * Rpad;
+    // FP32 partials (each already an FP32 sum; the splits are added in FP64)
+    float *pb = part + (int64_t)split * (int64_t)n1 * 4 * Rpad;
 #pragma unroll
     for (int nt = 0; nt < NTW; ++nt) {
         // n_z = 0: the four lane groups' sums, added in a fixed order
@@ -530,10 +531,10 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
         const int r = row0 + nt * 16 + ln;
         if (!rok[nt]) continue;
         if (g == 0) {
-            pb[0 * Rpad + r] = unscale_dc * dre;
-            pb[1 * (int64_t)Rpad + r] = unscale_dc * dim;
-            pb[2 * (int64_t)Rpad + r] = 0.0;
-            pb[3 * (int64_t)Rpad + r] = 0.0;
+            pb[0 * Rpad + r] = (float)(unscale_dc * dre);
+            pb[1 * (int64_t)Rpad + r] = (float)(unscale_dc * dim);
+            pb[2 * (int64_t)Rpad + r] = 0.f;
+            pb[3 * (int64_t)Rpad + r] = 0.f;
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -550,8 +551,8 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
                 } else {
                     continue;
                 }
-                pb[((int64_t)nz * 4 + slot) * Rpad + r] = outscale * (double)acc[mt][nt][0][i];
-                pb[((int64_t)nz * 4 + slot + 1) * Rpad + r] = outscale * (double)acc[mt][nt][1][i];
+                pb[((int64_t)nz * 4 + slot) * Rpad + r] = (float)(outscale * (double)acc[mt][nt][0][i]);
+                pb[((int64_t)nz * 4 + slot + 1) * Rpad + r] = (float)(outscale * (double)acc[mt][nt][1][i]);
             }
         }
     }
@@ -618,7 +619,7 @@ MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
 template <int MT>
 static void launch_dep_mt(hipStream_t s, const float *rec, int64_t N, const Geom &g,
                           const MfmaDepositPlan &pl, double unscale_mf, double unscale_dc,
-                          double *part)
+                          float *part)
 {
     // splits rounded up to whole groups of kXcds; blocks past the last split return
     const int groups = (pl.splits + kXcds - 1) / kXcds;
@@ -631,7 +632,7 @@ size_t deposit_mfma_rec_bytes(int64_t N, int n) { return (size_t)N * dep_rec_flo
 
 hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q, int64_t N,
                                const Geom &g, double L, const MfmaDepositPlan &pl, double qscale,
-                               float *rec, double *part)
+                               float *rec, float *part)
 {
     const dim3 pg((unsigned)((N + 255) / 256));
     const double qf = (double)kDepOpScale / qscale;

@@ -571,7 +571,7 @@ sce_status run_deposit_split(sce_ctx c)
     if (st) return st;
     size_t pb = c->part_bytes;
     void *pp = c->part;
-    st = ensure_bytes(c, pp, pb, (size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(double));
+    st = ensure_bytes(c, pp, pb, (size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(float));
     c->part = (double *)pp;
     c->part_bytes = pb;
     if (st) return st;
@@ -584,12 +584,12 @@ sce_status run_deposit_split(sce_ctx c)
     const bool tent = c->field == SCE_FIELD_TENT;
     if (tent) HIPCHK(c, sce::launch_tent_prep(c->stream, c->pos, c->q, c->N, c->dim, c->L, c->qw, c->env));
     HIPCHK(c, sce::launch_deposit_mfma(c->stream, c->pos, tent ? c->qw : c->q, c->N, g, c->L, pl,
-                                       c->qscale, (float *)c->turns, c->part));
+                                       c->qscale, (float *)c->turns, (float *)c->part));
     if (c->timing && ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_dep.push_back(ep);
     }
-    HIPCHK(c, sce::launch_reduce_solve<float>(c->stream, c->part, pl.splits, g, c->Stab, c->Gtab,
+    HIPCHK(c, sce::launch_reduce_solve<float>(c->stream, (const float *)c->part, pl.splits, g, c->Stab, c->Gtab,
                                               c->Ktab, c->rho, c->psi, (float *)c->ftab,
                                               (float *)c->psi0, c->wpart, &c->wblocks));
     if (tent)

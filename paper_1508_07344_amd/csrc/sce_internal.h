@@ -88,9 +88,10 @@ hipError_t launch_deposit(hipStream_t s, const double2 *exy, const T *tz, const 
 // per 64 cells (row, n_z); wpart holds 2 doubles per block).
 // ftab layout [R][nzp][8] of T: (sig_re, sig_im, del_re, del_im, nz del_re,
 // nz del_im, nz sig_re, nz sig_im) for n_z = 1..nzp with sig = psi(+nz) + psi(-nz),
-// del = psi(+nz) - psi(-nz); psi0 [R][2]: psi at n_z = 0.
-template <typename T>
-hipError_t launch_reduce_solve(hipStream_t s, const double *part, int splits, const Geom &g,
+// del = psi(+nz) - psi(-nz); psi0 [R][2]: psi at n_z = 0.  Partials P: FP64
+// from the direct deposits, FP32 from the matrix-core one (summed in FP64).
+template <typename T, typename P>
+hipError_t launch_reduce_solve(hipStream_t s, const P *part, int splits, const Geom &g,
                                const double *Stab, const double *Gtab, const double *Ktab,
                                double2 *rho, double2 *psi, T *ftab, T *psi0, double *wpart,
                                int *wblocks);
@@ -115,13 +116,13 @@ struct MfmaDepositPlan {
     int64_t perm;       // half width h of the Feistel visiting order (2^(2h) >= N)
 };
 MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N);
-// Deposit partial sums (same layout as launch_deposit).  rec: scratch of
+// Deposit partial sums (layout of launch_deposit, in FP32).  rec: scratch of
 // deposit_mfma_rec_bytes(N) for the per-particle records in visiting order;
 // charges enter scaled by 1/qscale and the partials leave scaled back.
 size_t deposit_mfma_rec_bytes(int64_t N, int n);
 hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q, int64_t N,
                                const Geom &g, double L, const MfmaDepositPlan &pl, double qscale,
-                               float *rec, double *part);
+                               float *rec, float *part);
 // Pack the FP32 force table into FP16 hi/lo matrix-core fragments in quads of
 // rows (each n_x line padded to whole quads), each row scaled by its
 // power-of-two scale s; rinfo (force_rowinfo_bytes) receives per padded row
