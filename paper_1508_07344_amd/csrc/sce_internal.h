@@ -124,9 +124,10 @@ hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q
                                const Geom &g, double L, const MfmaDepositPlan &pl, double qscale,
                                float *rec, float *part);
 // Pack the FP32 force table into FP16 hi/lo matrix-core fragments in quads of
-// rows (each n_x line padded to whole quads), each row scaled by its
-// power-of-two scale s; rinfo (force_rowinfo_bytes) receives per padded row
-// (psi(r,0) / s, 0, 0) and (n_x s, n_y s, s, 0).
+// rows (line 0, then one column of n_x = 1..n per n_y, each padded to whole
+// quads), each row scaled by its power-of-two scale s; rinfo
+// (force_rowinfo_bytes) receives per padded row (psi(r,0) / s, 0, 0) and
+// (n_x s, n_y s, s, 0).
 size_t force_pack_bytes(const Geom &g);
 size_t force_rowinfo_bytes(const Geom &g);
 hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0, const Geom &g,
