@@ -435,6 +435,12 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     }
 
     __syncthreads();  // chunk 0's tables
+    if (row0 >= R) {
+        // every row of this wave lies past the last row (the last row block of a
+        // grid whose rows do not fill it): only the block's barriers remain
+        for (int64_t c = 0; c < nchunks; ++c) __syncthreads();
+        return;
+    }
     // groups of 2^kDepFlipLog chunks; the running sums change sign between groups
     for (int64_t c0 = 0; c0 < nchunks; c0 += (1 << kDepFlipLog)) {
       const int64_t ce = c0 + (1 << kDepFlipLog) < nchunks ? c0 + (1 << kDepFlipLog) : nchunks;
