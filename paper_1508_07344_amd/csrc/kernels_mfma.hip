@@ -1031,13 +1031,17 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
     auto run_stage = [&](int st, const half8 *wl, half8 *next) {
         const int t0 = st * kForceTM;
         if (st + 1 < nstage) stage(st + 1, next);
+        // quads of the stage to multiply out: the whole stage but in the last
+        // one, whose padding quads past Q (zero weights) are skipped but for
+        // the one that completes a pair
+        const int cnt = fq.Q - t0 >= kForceTM ? kForceTM : ((fq.Q - t0 + 1) & ~1);
         f32x4 accA[NT], accB[NT];
         products(wl, 0, accA);
 #pragma unroll 1
-        for (int tt = 0; tt < kForceTM; tt += 2) {
+        for (int tt = 0; tt < cnt; tt += 2) {
             products(wl, tt + 1, accB);
             epilogue(wl, tt, t0 + tt, accA);
-            if (tt + 2 < kForceTM) products(wl, tt + 2, accA);
+            if (tt + 2 < cnt) products(wl, tt + 2, accA);
             epilogue(wl, tt + 1, t0 + tt + 1, accB);
         }
         // the next stage's copies have landed, and every wave is done with this one
