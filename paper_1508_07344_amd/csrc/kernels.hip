@@ -449,7 +449,8 @@ k_reduce_solve(const P *__restrict__ part, int splits, int n, int R, int Rpad, i
         }
         int nx, ny;
         row_nxny(row, n, nx, ny);
-        const double S = Stab[row * n1 + nz], G = Gtab[row * n1 + nz], K = Ktab[row * n1 + nz];
+        const int64_t ti = (int64_t)nz * R + row;  // tables are [n_z][row]: consecutive lanes, consecutive rows
+        const double S = Stab[ti], G = Gtab[ti], K = Ktab[ti];
         const double2 rp = make_double2(S * (Pr + Qi), S * (Pi - Qr));
         const double2 rm = make_double2(S * (Pr - Qi), S * (Pi + Qr));
         const bool hp = in_half(nx, ny, nz);

@@ -218,7 +218,7 @@ sce_status build_tables(sce_ctx c)
     double self = 0.0;
     for (int r = 0; r < g.R && c->field == SCE_FIELD_TENT; ++r)
         for (int nz = 0; nz <= g.n; ++nz) {
-            const size_t i = (size_t)r * g.n1 + nz;
+            const size_t i = (size_t)nz * g.R + r;  // [n_z][row]: rows fastest, as the reduce reads them
             S[i] = 1.0;
             G[i] = K[i] = 0.0;
         }
@@ -226,7 +226,7 @@ sce_status build_tables(sce_ctx c)
         int nx, ny;
         sce::row_nxny(r, g.n, nx, ny);
         for (int nz = 0; nz <= g.n; ++nz) {
-            const size_t i = (size_t)r * g.n1 + nz;
+            const size_t i = (size_t)nz * g.R + r;  // [n_z][row]: rows fastest, as the reduce reads them
             if (nx == 0 && ny == 0 && nz == 0) {
                 S[i] = G[i] = K[i] = 0.0;
                 continue;
