@@ -174,8 +174,10 @@ sce_status sce_set_options(sce_ctx ctx, double eps0, int32_t precision, int32_t 
  * Positions outside [0, L) are accepted and wrapped (kept as given in a
  * tent-field context).  Resets the step counter
  * and the cached force.  SCE_EINVAL if N < 1, N >= 2^32 or a pointer is
- * NULL; SCE_ENOMEM if the particle arrays do not fit in device memory (the
- * context then holds no particles). */
+ * NULL (nothing is changed), or if any x, v or q is not finite or any m is
+ * not finite and > 0 (checked on the device after the copy; the context then
+ * holds no particles); SCE_ENOMEM if the particle arrays do not fit in device
+ * memory (the context then holds no particles). */
 sce_status sce_set_particles(sce_ctx ctx, int64_t N, const double *x, const double *v,
                              const double *q, const double *m, int32_t on_device);
 
@@ -234,7 +236,10 @@ sce_status sce_diagnostics(sce_ctx ctx, sce_diag *out, double *rho_abs);
  * the step counter and the cached force.  SCE_EINVAL if *bytes is too small. */
 sce_status sce_get_state(sce_ctx ctx, void *buf, size_t *bytes);
 
-/* Restore a checkpoint written by sce_get_state for the same L and n_max. */
+/* Restore a checkpoint written by sce_get_state for the same L, n_max,
+ * dimension and field shape (SCE_EINVAL otherwise).  The saved force is
+ * reused only if the particle shape, its width, eps0 and the precision also
+ * match; otherwise the next step recomputes it at the restored positions. */
 sce_status sce_set_state(sce_ctx ctx, const void *buf, size_t bytes);
 
 /* Wait for all work on the context's stream. */

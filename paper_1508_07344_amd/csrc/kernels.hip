@@ -969,6 +969,34 @@ hipError_t launch_wrap(hipStream_t s, double *pos, int64_t N, double L)
     return hipGetLastError();
 }
 
+// Input check of a particle set: bit 0 of *flag for a non-finite position,
+// velocity or charge, bit 1 for a mass that is not finite and > 0.  *flag
+// must be zero before the launch.
+__global__ void __launch_bounds__(256)
+k_check_particles(const double *__restrict__ pos, const double *__restrict__ vel,
+                  const double *__restrict__ q, const double *__restrict__ m, int64_t N,
+                  unsigned *__restrict__ flag)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    unsigned bad = 0;
+    if (j < N) {
+        for (int d = 0; d < 3; ++d)
+            bad |= (isfinite(pos[d * N + j]) && isfinite(vel[d * N + j])) ? 0u : 1u;
+        bad |= isfinite(q[j]) ? 0u : 1u;
+        bad |= (isfinite(m[j]) && m[j] > 0.0) ? 0u : 2u;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+hipError_t launch_check_particles(hipStream_t s, const double *pos, const double *vel,
+                                  const double *q, const double *m, int64_t N, unsigned *flag)
+{
+    const int64_t blocks = (N + 255) / 256;
+    hipLaunchKernelGGL(k_check_particles, dim3((unsigned)blocks), dim3(256), 0, s, pos, vel, q, m,
+                       N, flag);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ diagnostics
 // scratch: [blocks][6] partial sums, written in block order.
 __global__ void __launch_bounds__(256)

@@ -589,6 +589,10 @@ size_t deposit_mfma_lds(int n)
 // per CU.  The split count is a multiple of kXcds (the XCD-aware numbering
 // needs whole groups) chosen to minimise rounds per particle, i.e. to avoid a
 // last round that is nearly empty; ties go to fewer splits (fewer partials).
+// A split holds at most kDepMaxRun particles: its matrix-core sums run in FP32
+// over the whole split, so their length is bounded whatever N is (more
+// particles mean more splits and FP64 cross-split sums instead).
+constexpr int64_t kDepMaxRun = 8192;
 MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
 {
     MfmaDepositPlan p;
@@ -600,9 +604,11 @@ MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
     if (cus < 1) cus = 256;
     const int64_t smax = N / 512 >= kXcds ? (N / 512) / kXcds * kXcds : 0;
     int64_t splits = N / 512 > 1 ? N / 512 : 1;  // small N: fewer splits than one XCD group
+    // fewest splits that keep every run within kDepMaxRun, in whole XCD groups
+    const int64_t smin = ((N + kDepMaxRun - 1) / kDepMaxRun + kXcds - 1) / kXcds * kXcds;
     if (smax >= kXcds) {
         double best = 1e300;
-        for (int64_t sp = kXcds; sp <= smax && sp <= 4096; sp += kXcds) {
+        for (int64_t sp = smin > kXcds ? smin : kXcds; sp <= smax && sp <= (int64_t)1 << 20; sp += kXcds) {
             const int64_t blocks = (int64_t)p.row_blocks * sp;
             const double cost = (double)((blocks + cus - 1) / cus) / (double)sp;
             if (cost < best * (1.0 - 1e-9)) {

@@ -838,11 +838,24 @@ sce_status sce_set_particles(sce_ctx c, int64_t N, const double *x, const double
     }
     if ((st = copy_in(c, c->q, q, N * sizeof(double), on_device))) return st;
     if ((st = copy_in(c, c->m, m, N * sizeof(double), on_device))) return st;
+    // reject non-finite values and non-positive masses before anything uses them
+    unsigned *flag = reinterpret_cast<unsigned *>(c->dout);
+    unsigned bad = 0;
+    HIPCHK(c, hipMemsetAsync(flag, 0, sizeof(unsigned), c->stream));
+    HIPCHK(c, sce::launch_check_particles(c->stream, c->pos, c->vel, c->q, c->m, N, flag));
     if (c->field != SCE_FIELD_TENT) HIPCHK(c, sce::launch_wrap(c->stream, c->pos, N, c->L));
     // sum q^2 for the self-energy (host copy of q)
     std::vector<double> hq(N);
     HIPCHK(c, hipMemcpyAsync(hq.data(), c->q, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&bad, flag, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) {
+        c->N = 0;
+        c->gen++;
+        c->fields_valid = c->force_valid = c->phi_valid = false;
+        return fail(c, SCE_EINVAL, (bad & 1) ? "non-finite position, velocity or charge"
+                                             : "every mass must be finite and > 0");
+    }
     double s = 0.0, qmax = 0.0;
     for (double v_ : hq) {
         s += v_ * v_;
@@ -1144,8 +1157,12 @@ struct StateHeader {
     int32_t has_force;
     int32_t dim;
     int32_t field;
+    int32_t kind;
+    int32_t prec;
+    double width;
+    double eps0;
 };
-const uint64_t kMagic = 0x32454353484b5053ull;  // "SPKHSCE2"
+const uint64_t kMagic = 0x33454353484b5053ull;  // "SPKHSCE3"
 }  // namespace
 
 sce_status sce_get_state(sce_ctx c, void *buf, size_t *bytes)
@@ -1161,7 +1178,7 @@ sce_status sce_get_state(sce_ctx c, void *buf, size_t *bytes)
     }
     if (*bytes < need) return fail(c, SCE_EINVAL, "buffer too small");
     StateHeader hd{kMagic, c->N, c->step, c->time, c->L, c->g.n, c->force_valid ? 1 : 0, c->dim,
-                   c->field};
+                   c->field, c->kind, c->prec, c->width, c->eps0};
     std::memcpy(buf, &hd, sizeof(hd));
     double *d = (double *)((char *)buf + sizeof(hd));
     const size_t n3 = 3 * c->N * sizeof(double), n1 = c->N * sizeof(double);
@@ -1191,7 +1208,12 @@ sce_status sce_set_state(sce_ctx c, const void *buf, size_t bytes)
     // the arrays are stored as (x, y, z); a 2-D context takes its (x, y) = stored (y, z)
     const int64_t off = c->dim == 2 ? N : 0;
     if ((st = sce_set_particles(c, N, d + off, d + 3 * N + off, d + 6 * N, d + 7 * N, 0))) return st;
-    if (hd.has_force) {
+    // the saved force belongs to the saved field: reuse it only when the shape,
+    // its width, eps0 and the precision match; otherwise the next step
+    // recomputes it
+    const bool same_field = hd.kind == c->kind && hd.width == c->width && hd.eps0 == c->eps0 &&
+                            hd.prec == c->prec;
+    if (hd.has_force && same_field) {
         if ((st = copy_in(c, c->F, d + 8 * N, 3 * N * sizeof(double), 0))) return st;
         c->force_valid = true;
     }

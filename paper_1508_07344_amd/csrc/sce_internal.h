@@ -140,6 +140,12 @@ hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, 
 hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *F,
                              const double *m, int64_t N, double L, double a, double b, bool wrap);
 
+// Flag bad particle input (kernels.hip k_check_particles): *flag |= 1 for a
+// non-finite x, v or q, |= 2 for a mass that is not finite and > 0.  The
+// caller zeroes *flag first.
+hipError_t launch_check_particles(hipStream_t s, const double *pos, const double *vel,
+                                  const double *q, const double *m, int64_t N, unsigned *flag);
+
 // Wrap positions into [0, L).
 hipError_t launch_wrap(hipStream_t s, double *pos, int64_t N, double L);
 

@@ -81,10 +81,18 @@ def test_deposit_and_force_match_oracle(references, name, prec):
         rho = c.sce_deposit()
         psi = c.sce_psi()
         F = c.sce_force()
-        d, st = c.sce_diagnostics()
+        d, rho_abs, st = c.sce_diagnostics(rho_abs=True)
     er, ep, ef = e_rho(rho, ref.rho), e_rho(psi, ref.psi), e_F(F, ref.F) if p.N > 1 else 0.0
     print(f"{name} {prec}: e_rho={er:.3e} e_psi={ep:.3e} e_F={ef:.3e}")
     assert er <= TOL[prec] and ep <= TOL[prec]
+    # diagnostics: the |rho| export and its maximum against the oracle's rho,
+    # the constant self-energy against the oracle's (host FP64 in every precision)
+    ref_abs = np.abs(ref.rho)
+    assert np.max(np.abs(rho_abs - ref_abs)) <= TOL[prec] * np.max(ref_abs)
+    assert abs(d.rho_abs_max - np.max(ref_abs)) <= TOL[prec] * np.max(ref_abs)
+    modes = oracle.half_modes(p.n_max)
+    w_self = oracle.self_energy(p.q, p.L, modes, p.eps0, p.shape, p.a)
+    assert abs(d.field_self - w_self) <= 1e-12 * w_self
     if p.N > 1:
         assert ef <= TOL[prec]
     else:  # lone particle: no self-force, relative to the scale of one mode sum
@@ -339,3 +347,64 @@ def test_out_of_device_memory_leaves_the_context_usable():
         F = c.sce_force()
         c.sce_step(p.dt, 3)
     assert e_F(F, ref.F) <= TOL["fp64"]
+
+
+def test_non_finite_energy_is_unstable():
+    """A velocity whose kinetic energy overflows (v = 1e300) makes the total
+    energy non-finite: sce_diagnostics fills the record and returns
+    SCE_EUNSTABLE."""
+    sce = _gpu()
+    p = workloads.random_plasma(N=300, n_max=4, a=0.05, salt=21)
+    p.vx[7] = 1e300
+    with sce.Context.from_particles(p) as c:
+        d, st = c.sce_diagnostics(allow_unstable=True)
+        assert st == sce.SCE_EUNSTABLE and not math.isfinite(d.total)
+        with pytest.raises(sce.SceError) as ei:
+            c.sce_diagnostics()
+        assert ei.value.status == sce.SCE_EUNSTABLE
+
+
+@pytest.mark.parametrize("field,value", [("x", float("nan")), ("vz", float("inf")), ("q", float("-inf")),
+                                         ("m", 0.0), ("m", -1.0), ("m", float("nan"))])
+def test_set_particles_rejects_non_finite_input(field, value):
+    """Non-finite positions, velocities or charges and masses that are not
+    finite and > 0 are SCE_EINVAL; the context then holds no particles and
+    takes a valid set again."""
+    sce = _gpu()
+    p = workloads.random_plasma(N=1000, n_max=5, a=0.05, salt=22)
+    bad = p.copy()
+    getattr(bad, field)[613] = value
+    ref = oracle.fields(p.positions(), p.q, p.L, p.n_max, p.shape, p.a, p.eps0)
+    with sce.Context(p.L, p.n_max, p.shape, p.a) as c:
+        with pytest.raises(sce.SceError) as ei:
+            c.sce_set_particles(bad.positions(), bad.velocities(), bad.q, bad.m)
+        assert ei.value.status == sce.SCE_EINVAL
+        with pytest.raises(sce.SceError) as ei:
+            c.sce_force()
+        assert ei.value.status == sce.SCE_ESTATE
+        c.sce_set_particles(p.positions(), p.velocities(), p.q, p.m)
+        assert e_F(c.sce_force(), ref.F) <= TOL["fp64"]
+
+
+def test_checkpoint_into_another_field_recomputes_the_force():
+    """A checkpoint restored into a context with another eps0 (or shape width,
+    or precision) keeps the particles but not the saved force: the next step
+    equals a step from freshly set particles in that context."""
+    sce = _gpu()
+    p = workloads.random_plasma(N=2000, n_max=6, a=0.05, salt=23, sigma_v=0.05)
+    with sce.Context.from_particles(p) as c:
+        c.sce_step(p.dt, 3)
+        blob = c.sce_get_state()
+        x3, v3 = c.sce_get_particles()
+    q2 = p.with_(eps0=0.5)
+    out = []
+    for restore in (True, False):
+        with sce.Context(p.L, p.n_max, p.shape, p.a) as c2:
+            c2.sce_set_options(0.5, "fp64", "kdk")
+            if restore:
+                c2.sce_set_state(blob)
+            else:
+                c2.sce_set_particles(x3, v3, q2.q, q2.m)
+            c2.sce_step(p.dt, 2)
+            out.append(c2.sce_get_particles())
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
