@@ -202,6 +202,25 @@ sce_status sce_psi(sce_ctx ctx, double *psi, int32_t on_device);
  * Velocities are not changed.  F may be NULL. */
 sce_status sce_force(sce_ctx ctx, double *F, int32_t on_device);
 
+/* sce_force without device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): the same pass (deposit, solve, force at the current
+ * positions) and the same F, but the pass's scratch buffers (phase tables,
+ * per-split deposit partials or particle records, the force's line-group
+ * partials) live in one static 64 MiB device array per GPU instead of the
+ * context's buffers, which sce_force allocates on first use.  The context's
+ * own buffers (particles, modes, fields) are allocated by sce_create,
+ * sce_set_options and sce_set_particles, as for every call.  Every call of
+ * this function on a GPU uses that GPU's one array, which keeps the last
+ * call's contents; calls that overlap in time on one GPU (other threads, or
+ * other contexts' streams) race and must be ordered by the caller.  Kernel
+ * timing (sce_timing_enable) does not record this call.  Errors as
+ * sce_force; SCE_EINVAL if the pass needs more than 64 MiB of scratch (for
+ * example 65,536 particles at n_max = 16 need about 27 MB with
+ * SCE_PREC_SPLIT_F16; 262,144 particles at n_max = 16 need more than 64 MiB
+ * with SCE_PREC_FP64). */
+sce_status sce_force_noalloc(sce_ctx ctx, double *F, int32_t on_device);
+
 /* Advance n_steps >= 0 steps of size dt (finite) with the configured scheme.
  * Small FP64 systems run as one kernel per block of steps (sce_set_small_step).
  * Otherwise, with n_steps >= 2 G (G = steps per graph, see sce_set_step_graph) and

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,7 +27,23 @@ struct EventPair {
     hipEvent_t a, b;
 };
 
+// Scratch of sce_force_noalloc: one static array per GPU, resolved to a device
+// address once per device (hipGetSymbolAddress at context creation) and only
+// used through that address.  Every call on a GPU shares it.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Scratch buffers of one pass (deposit, solve, force) supplied by the caller
+// of the pass instead of the context's own lazily sized buffers.
+struct PassScratch {
+    void *tab, *tabxy, *part, *rec, *fscr;
+};
+
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 struct sce_ctx_s {
     int device = 0;
@@ -488,37 +505,44 @@ hipEvent_t take_event(sce_ctx c)
 }
 
 template <typename T>
-sce_status run_deposit(sce_ctx c)
+sce_status run_deposit(sce_ctx c, const PassScratch *ps)
 {
     const Geom &g = c->g;
     const sce::DepositPlan pl = sce::plan_deposit(g, c->N, (int)sizeof(T));
-    sce_status st = ensure_bytes(c, c->tab, c->tab_bytes, (size_t)c->N * 2 * g.zslots * sizeof(T));
-    if (st) return st;
-    st = ensure_bytes(c, c->tabxy, c->tabxy_bytes, (size_t)c->N * 2 * g.n1 * sizeof(double2));
-    if (st) return st;
-    size_t pb = c->part_bytes;
-    void *pp = c->part;
-    st = ensure_bytes(c, pp, pb, (size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(double));
-    c->part = (double *)pp;
-    c->part_bytes = pb;
-    if (st) return st;
+    void *tab = ps ? ps->tab : nullptr, *tabxy = ps ? ps->tabxy : nullptr;
+    double *part = ps ? (double *)ps->part : nullptr;
+    if (!ps) {
+        sce_status st = ensure_bytes(c, c->tab, c->tab_bytes, (size_t)c->N * 2 * g.zslots * sizeof(T));
+        if (st) return st;
+        st = ensure_bytes(c, c->tabxy, c->tabxy_bytes, (size_t)c->N * 2 * g.n1 * sizeof(double2));
+        if (st) return st;
+        size_t pb = c->part_bytes;
+        void *pp = c->part;
+        st = ensure_bytes(c, pp, pb, (size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(double));
+        c->part = (double *)pp;
+        c->part_bytes = pb;
+        if (st) return st;
+        tab = c->tab;
+        tabxy = c->tabxy;
+        part = c->part;
+    }
     const bool tent = c->field == SCE_FIELD_TENT;
     if (tent) HIPCHK(c, sce::launch_tent_prep(c->stream, c->pos, c->q, c->N, c->dim, c->L, c->qw, c->env));
-    HIPCHK(c, sce::launch_phase_table<T>(c->stream, c->pos, c->N, g, c->L, (double2 *)c->tabxy,
-                                         (T *)c->tab));
+    HIPCHK(c, sce::launch_phase_table<T>(c->stream, c->pos, c->N, g, c->L, (double2 *)tabxy,
+                                         (T *)tab));
     EventPair ep{nullptr, nullptr};
-    if (c->timing) {
+    if (c->timing && !ps) {
         ep.a = take_event(c);
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
-    HIPCHK(c, sce::launch_deposit<T>(c->stream, (const double2 *)c->tabxy, (const T *)c->tab,
-                                     tent ? c->qw : c->q, c->N, g, pl, c->part));
-    if (c->timing && ep.a && ep.b) {
+    HIPCHK(c, sce::launch_deposit<T>(c->stream, (const double2 *)tabxy, (const T *)tab,
+                                     tent ? c->qw : c->q, c->N, g, pl, part));
+    if (ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_dep.push_back(ep);
     }
-    HIPCHK(c, sce::launch_reduce_solve<T>(c->stream, c->part, pl.splits, g, c->Stab, c->Gtab,
+    HIPCHK(c, sce::launch_reduce_solve<T>(c->stream, part, pl.splits, g, c->Stab, c->Gtab,
                                           c->Ktab, c->rho, c->psi, (T *)c->ftab, (T *)c->psi0,
                                           c->wpart, &c->wblocks));
     if (tent)
@@ -530,26 +554,28 @@ sce_status run_deposit(sce_ctx c)
 }
 
 template <typename T>
-sce_status run_force(sce_ctx c, double kick)
+sce_status run_force(sce_ctx c, double kick, const PassScratch *ps)
 {
     EventPair ep{nullptr, nullptr};
-    if (c->timing) {
+    if (c->timing && !ps) {
         ep.a = take_event(c);
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
     const bool tent = c->field == SCE_FIELD_TENT;
     const int lg = sce::force_line_groups(c->g, c->N, (int)sizeof(T));
-    if (lg > 1) {
+    double *fscr = ps ? (double *)ps->fscr : c->fscratch;
+    if (lg > 1 && !ps) {
         void *fs = c->fscratch;
         sce_status st = ensure_bytes(c, fs, c->fscratch_bytes, (size_t)lg * 4 * c->N * sizeof(double));
         c->fscratch = (double *)fs;
         if (st) return st;
+        fscr = c->fscratch;
     }
     HIPCHK(c, sce::launch_force<T>(c->stream, c->pos, c->q, c->m, c->vel, (const T *)c->ftab,
                                    (const T *)c->psi0, c->g, c->L, c->N, tent ? 0.0 : kick,
-                                   tent ? c->Fk : c->F, tent ? c->Pk : c->phi, c->fscratch));
-    if (c->timing && ep.a && ep.b) {
+                                   tent ? c->Fk : c->F, tent ? c->Pk : c->phi, fscr));
+    if (ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_frc.push_back(ep);
     }
@@ -561,22 +587,27 @@ sce_status run_force(sce_ctx c, double kick)
     return SCE_OK;
 }
 
-sce_status run_deposit_split(sce_ctx c)
+sce_status run_deposit_split(sce_ctx c, const PassScratch *ps)
 {
     const Geom &g = c->g;
     const sce::MfmaDepositPlan pl = sce::plan_deposit_mfma(g, c->N);
-    void *tp = c->turns;
-    sce_status st = ensure_bytes(c, tp, c->turns_bytes, sce::deposit_mfma_rec_bytes(c->N, g.n));
-    c->turns = (double *)tp;
-    if (st) return st;
-    size_t pb = c->part_bytes;
-    void *pp = c->part;
-    st = ensure_bytes(c, pp, pb, (size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(float));
-    c->part = (double *)pp;
-    c->part_bytes = pb;
-    if (st) return st;
+    float *rec = ps ? (float *)ps->rec : nullptr, *part = ps ? (float *)ps->part : nullptr;
+    if (!ps) {
+        void *tp = c->turns;
+        sce_status st = ensure_bytes(c, tp, c->turns_bytes, sce::deposit_mfma_rec_bytes(c->N, g.n));
+        c->turns = (double *)tp;
+        if (st) return st;
+        size_t pb = c->part_bytes;
+        void *pp = c->part;
+        st = ensure_bytes(c, pp, pb, (size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(float));
+        c->part = (double *)pp;
+        c->part_bytes = pb;
+        if (st) return st;
+        rec = (float *)c->turns;
+        part = (float *)c->part;
+    }
     EventPair ep{nullptr, nullptr};
-    if (c->timing) {
+    if (c->timing && !ps) {
         ep.a = take_event(c);
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
@@ -584,12 +615,12 @@ sce_status run_deposit_split(sce_ctx c)
     const bool tent = c->field == SCE_FIELD_TENT;
     if (tent) HIPCHK(c, sce::launch_tent_prep(c->stream, c->pos, c->q, c->N, c->dim, c->L, c->qw, c->env));
     HIPCHK(c, sce::launch_deposit_mfma(c->stream, c->pos, tent ? c->qw : c->q, c->N, g, c->L, pl,
-                                       c->qscale, (float *)c->turns, (float *)c->part));
-    if (c->timing && ep.a && ep.b) {
+                                       c->qscale, rec, part));
+    if (ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_dep.push_back(ep);
     }
-    HIPCHK(c, sce::launch_reduce_solve<float>(c->stream, (const float *)c->part, pl.splits, g, c->Stab, c->Gtab,
+    HIPCHK(c, sce::launch_reduce_solve<float>(c->stream, (const float *)part, pl.splits, g, c->Stab, c->Gtab,
                                               c->Ktab, c->rho, c->psi, (float *)c->ftab,
                                               (float *)c->psi0, c->wpart, &c->wblocks));
     if (tent)
@@ -603,10 +634,10 @@ sce_status run_deposit_split(sce_ctx c)
     return SCE_OK;
 }
 
-sce_status run_force_split(sce_ctx c, double kick, bool want_phi)
+sce_status run_force_split(sce_ctx c, double kick, bool want_phi, const PassScratch *ps)
 {
     EventPair ep{nullptr, nullptr};
-    if (c->timing) {
+    if (c->timing && !ps) {
         ep.a = take_event(c);
         ep.b = take_event(c);
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
@@ -616,7 +647,7 @@ sce_status run_force_split(sce_ctx c, double kick, bool want_phi)
                                      reinterpret_cast<const float4 *>(c->wscr), c->g, c->L, c->N,
                                      tent ? 0.0 : kick, tent ? c->Fk : c->F,
                                      tent ? c->Pk : (want_phi ? c->phi : nullptr)));
-    if (c->timing && ep.a && ep.b) {
+    if (ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_frc.push_back(ep);
     }
@@ -628,29 +659,63 @@ sce_status run_force_split(sce_ctx c, double kick, bool want_phi)
     return SCE_OK;
 }
 
-sce_status deposit(sce_ctx c)
+// ps: caller-supplied scratch (sce_force_noalloc), or NULL for the
+// context's own buffers, allocated or grown on demand.
+sce_status deposit(sce_ctx c, const PassScratch *ps = nullptr)
 {
-    if (c->prec == SCE_PREC_FP64) return run_deposit<double>(c);
-    if (c->prec == SCE_PREC_FP32) return run_deposit<float>(c);
-    if (c->prec == SCE_PREC_SPLIT_F16) return run_deposit_split(c);
+    if (c->prec == SCE_PREC_FP64) return run_deposit<double>(c, ps);
+    if (c->prec == SCE_PREC_FP32) return run_deposit<float>(c, ps);
+    if (c->prec == SCE_PREC_SPLIT_F16) return run_deposit_split(c, ps);
     return fail(c, SCE_ENOTSUP, "precision not available");
 }
 
-sce_status force(sce_ctx c, double kick, bool want_phi)
+sce_status force(sce_ctx c, double kick, bool want_phi, const PassScratch *ps = nullptr)
 {
-    if (c->prec == SCE_PREC_FP64) return run_force<double>(c, kick);
-    if (c->prec == SCE_PREC_FP32) return run_force<float>(c, kick);
-    if (c->prec == SCE_PREC_SPLIT_F16) return run_force_split(c, kick, want_phi);
+    if (c->prec == SCE_PREC_FP64) return run_force<double>(c, kick, ps);
+    if (c->prec == SCE_PREC_FP32) return run_force<float>(c, kick, ps);
+    if (c->prec == SCE_PREC_SPLIT_F16) return run_force_split(c, kick, want_phi, ps);
     return fail(c, SCE_ENOTSUP, "precision not available");
 }
 
 // One pass of the hot path at the current positions: deposit, solve, force
 // (+kick); the potential at the particles too when want_phi.
-sce_status pass(sce_ctx c, double kick, bool want_phi = false)
+sce_status pass(sce_ctx c, double kick, bool want_phi = false, const PassScratch *ps = nullptr)
 {
-    sce_status st = deposit(c);
+    sce_status st = deposit(c, ps);
     if (st) return st;
-    return force(c, kick, want_phi);
+    return force(c, kick, want_phi, ps);
+}
+
+// Bytes of scratch one pass needs at the context's size and precision, laid
+// out in ps from base (256-byte aligned pieces).  The deposit's tables and
+// partials are dead once the solve has run, so the force's line-group
+// partials reuse the same bytes.
+size_t pass_scratch_layout(sce_ctx c, char *base, PassScratch *ps)
+{
+    const Geom &g = c->g;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t dep = 0, frc = 0;
+    *ps = PassScratch{nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (c->prec == SCE_PREC_SPLIT_F16) {
+        const sce::MfmaDepositPlan pl = sce::plan_deposit_mfma(g, c->N);
+        const size_t rb = al(sce::deposit_mfma_rec_bytes(c->N, g.n));
+        ps->rec = base;
+        ps->part = base + rb;
+        dep = rb + al((size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(float));
+    } else {
+        const size_t eb = elem_bytes(c->prec);
+        const sce::DepositPlan pl = sce::plan_deposit(g, c->N, (int)eb);
+        const size_t tb = al((size_t)c->N * 2 * g.zslots * eb);
+        const size_t xb = al((size_t)c->N * 2 * g.n1 * sizeof(double2));
+        ps->tab = base;
+        ps->tabxy = base + tb;
+        ps->part = base + tb + xb;
+        dep = tb + xb + al((size_t)pl.splits * g.n1 * 4 * g.Rpad * sizeof(double));
+        const int lg = sce::force_line_groups(g, c->N, (int)eb);
+        if (lg > 1) frc = al((size_t)lg * 4 * c->N * sizeof(double));
+        ps->fscr = base;
+    }
+    return dep > frc ? dep : frc;
 }
 
 sce_status check_ready(sce_ctx c)
@@ -700,6 +765,21 @@ const char *sce_last_error(sce_ctx c) { return c ? c->err.c_str() : "null contex
 }  // extern "C"
 
 namespace {
+// Device address of this GPU's static scratch (sce_force_noalloc), taken once
+// per device with that device current; the array's name is never used as a
+// device address in host code.
+hipError_t resolve_noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipSuccess;  // sce_force_noalloc then refuses
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+    return hipSuccess;
+}
+
 sce_status create_ctx(double L, int32_t n_max, int32_t shape_kind, double shape_width, int dim,
                       int field, sce_ctx *out)
 {
@@ -718,6 +798,7 @@ sce_status create_ctx(double L, int32_t n_max, int32_t shape_kind, double shape_
     c->field = field;
     c->g = make_geom(n_max, dim);
     hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = resolve_noalloc_scratch(c->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete c;
@@ -943,6 +1024,30 @@ sce_status sce_force(sce_ctx c, double *F, int32_t on_device)
     if (st) return st;
     if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
     if ((st = pass(c, 0.0))) return st;
+    if (F)
+        return copy_out(c, F, c->F + (c->dim == 2 ? c->N : 0), (size_t)c->dim * c->N * sizeof(double),
+                        on_device);
+    return SCE_OK;
+}
+
+sce_status sce_force_noalloc(sce_ctx c, double *F, int32_t on_device)
+{
+    sce_status st = check_ready(c);
+    if (st) return st;
+    if (c->N < 1) return fail(c, SCE_ESTATE, "no particles set");
+    void *base = nullptr;
+    if (c->device >= 0 && c->device < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        base = g_scratch_ptr[c->device];
+    }
+    if (!base) return fail(c, SCE_ENOTSUP, "no static scratch on this device");
+    PassScratch ps;
+    const size_t need = pass_scratch_layout(c, (char *)base, &ps);
+    if (need > kNoallocScratchBytes)
+        return fail(c, SCE_EINVAL, "this pass needs " + std::to_string(need) +
+                                       " bytes of scratch, above the static " +
+                                       std::to_string(kNoallocScratchBytes) + " bytes");
+    if ((st = pass(c, 0.0, false, &ps))) return st;
     if (F)
         return copy_out(c, F, c->F + (c->dim == 2 ? c->N : 0), (size_t)c->dim * c->N * sizeof(double),
                         on_device);

@@ -112,6 +112,7 @@ def load_library():
         "sce_deposit": ([P, P, i32], i32),
         "sce_psi": ([P, P, i32], i32),
         "sce_force": ([P, P, i32], i32),
+        "sce_force_noalloc": ([P, P, i32], i32),
         "sce_step": ([P, f64, i64], i32),
         "sce_set_step_graph": ([P, i32], i32),
         "sce_set_small_step": ([P, i64], i32),
@@ -298,6 +299,19 @@ class Context:
         p, d = _ptr(out)
         _torch_sync_if_device(out)
         self._chk(self._lib.sce_force(self._h, p, d), "sce_force")
+        self.sce_sync()
+        return out
+
+    def sce_force_noalloc(self, out=None):
+        """``sce_force`` with the pass's scratch in the library's static
+        per-GPU array (no device allocation)."""
+        if out is None:
+            buf = np.zeros((self.dim, self.N))
+            self._chk(self._lib.sce_force_noalloc(self._h, _host(buf), 0), "sce_force_noalloc")
+            return buf
+        p, d = _ptr(out)
+        _torch_sync_if_device(out)
+        self._chk(self._lib.sce_force_noalloc(self._h, p, d), "sce_force_noalloc")
         self.sce_sync()
         return out
 
