@@ -72,17 +72,19 @@ __device__ inline f32x4 mfma_split(half8 ah, half8 al, half8 bh, half8 bl, f32x4
 // affine order i*A mod N is a rank-1 lattice and stays coherent for some wave
 // vectors).  The order is a bijection of [0, N): a 4-round Feistel network on
 // 2h bits (2^(2h) >= N), each round (L, R) -> (R, L ^ f_r(R)), with cycle
-// walking back into [0, N).  Particle j's record goes to slot feistel_inv(j).
+// walking back into [0, N).  Slot s of the visiting order holds particle
+// feistel_fwd(s).
 
 // ------------------------------------------------------------------ deposit
 // Particles are taken in chunks of 32 (the K depth of one matrix instruction).
 constexpr int kDepChunk = 32;
 // Both deposit operands are multiplied by 7/8 before the split (and the
-// result by 64/49 in FP64).  Unscaled, cos(n_z theta) and h crowd just below
-// 1.0 for particles near the origin, where round-to-nearest FP16 gives hi = 1
-// and a negative lo in both operands: the dropped lo*lo term then has a
-// consistent sign and acts like a spurious charge at the origin.  At 7/8 no
-// operand sits at an FP16 exponent boundary and the lo parts are unbiased.
+// result by 64/49 in FP64).  Unscaled, cos(n_z theta) and the x-y products
+// crowd just below 1.0 for particles near the origin, where round-to-nearest
+// FP16 gives hi = 1 and a negative lo in both operands: the dropped lo*lo term
+// then has a consistent sign and acts like a spurious charge at the origin.
+// At 7/8 no operand sits at an FP16 exponent boundary and the lo parts are
+// unbiased.
 constexpr float kDepOpScale = 0.875f;
 // The matrix core rounds its FP32 accumulation per group of products and, when
 // the running sum is much larger than each increment, slightly toward -inf.
@@ -90,89 +92,232 @@ constexpr float kDepOpScale = 0.875f;
 // accumulator and would act like a spurious charge at the origin.  The running
 // sum therefore changes sign every 2^kDepFlipLog chunks (accumulator and CS
 // operand negated together), so the bias alternates direction and cancels.
+constexpr int kDepFlipLog = 3;
+// FP32 sums of the n_z = 0 row are added into FP64 every 2^kDepDcLog chunks.
+constexpr int kDepDcLog = 4;
 
-// Per-particle record in visiting order, FP32, for nb = ceil((n+1)/8) blocks
-// of 8 powers per axis: [d][blk] = cis(2 pi 8 blk t_d) (anchors, formed in
-// FP64), then [d] = cis(2 pi t_d) (steps), then the scaled charge
-// (q / max|q|) * 7/8; padded to a multiple of 4 floats.
-__host__ __device__ inline int dep_rec_floats(int n)
+__host__ __device__ inline uint32_t feistel_round(uint32_t x, int r)
 {
-    const int nb = (n + 1 + 7) / 8;
-    return (3 * (nb + 1) * 2 + 1 + 3) / 4 * 4;
+    uint32_t f = x * 0x9E3779B1u + 0x7F4A7C15u * (uint32_t)(r + 1);
+    f ^= f >> 15;
+    f *= 0x85EBCA6Bu;
+    f ^= f >> 13;
+    return f;
 }
 
-// Inverse of the visiting-order map: its rounds undone in reverse order,
-// walking back into [0, N) the way the forward map walks out of it.
-__device__ inline uint32_t feistel_inv(uint32_t j, uint32_t N, int h)
+// The visiting-order map: slot s -> particle, rounds applied in order and
+// repeated while the result lies outside [0, N) (cycle walking).
+__host__ __device__ inline uint32_t feistel_fwd(uint32_t s, uint32_t N, int h)
 {
     const uint32_t mask = h >= 16 ? 0xFFFFu : ((1u << h) - 1u);
-    uint32_t y = j;
+    uint32_t y = s;
     do {
         uint32_t L = y >> h, R = y & mask;
-#pragma unroll
-        for (int r = 3; r >= 0; --r) {
-            uint32_t f = L * 0x9E3779B1u + 0x7F4A7C15u * (uint32_t)(r + 1);
-            f ^= f >> 15;
-            f *= 0x85EBCA6Bu;
-            f ^= f >> 13;
-            const uint32_t pl = (R ^ f) & mask;
-            R = L;
-            L = pl;
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t nr = (L ^ feistel_round(R, r)) & mask;
+            L = R;
+            R = nr;
         }
         y = (L << h) | R;
     } while (y >= N);
     return y;
 }
 
-// Thread j takes particle j (coalesced reads) and writes its record at its
-// place in the visiting order, feistel_inv(j), as 16-byte stores; NB anchor
-// blocks per axis, so the record sits in registers with static indices.
-template <int NB>
-__global__ void __launch_bounds__(256)
-k_deposit_prep(const double *__restrict__ pos, const double *__restrict__ q, int64_t N,
-               double invL, int h, double qfac, float *__restrict__ rec)
+// Chunk image: the LDS tables of one chunk of 32 particles p of the visiting
+// order, exactly as the matrix-core kernel reads them (it copies images into
+// LDS unchanged):
+//   CS hi, CS lo: the A operand, cos and sin(2 pi n_z t_z) for n_z = 1..n
+//       (rows 0..n-1 and n..2n-1, zero rows up to 16 MT), times the running-sum
+//       sign and 7/8, as FP16 halves in the matrix core's fragment order
+//       (cs_idx), so that a lane's 16-byte fragment read sits at 16 lane +
+//       const: 16-byte LDS reads run at full rate only when the lanes'
+//       addresses are consecutive;
+//   X[p][k] = q' (cos, sin)(2 pi k t_x), k = 0..n, q' = (7/8) q / max|q|;
+//   Y[p][k] = (cos, sin)(2 pi k t_y), k = 0..n.
+// X and Y rows have a compile-time stride (k = 0..8 MT, the largest n_max of
+// the tile class) rounded up to 2 (mod 4) float2 entries, so the rows of
+// particles p and p + 8, which lane groups 0/1 (and 2/3) read in the same pass
+// of an 8-byte read, start 128 bytes apart modulo the 256-byte bank cycle.
+// An image is a whole number of KB.
+template <int MT>
+struct DepTab {
+    static constexpr int kmax = 8 * MT + 1;
+    static constexpr int sxy = kmax + (6 - kmax % 4) % 4;  // = 2 (mod 4)
+    static constexpr int cs_halves = MT * 16 * kDepChunk;   // one of hi, lo
+    static constexpr size_t x_off = (size_t)2 * cs_halves * sizeof(_Float16);
+    static constexpr size_t y_off = x_off + (size_t)kDepChunk * sxy * sizeof(float2);
+    static constexpr size_t bytes = y_off + (size_t)kDepChunk * sxy * sizeof(float2);
+    static_assert(bytes % 1024 == 0, "whole KB");
+};
+// CS element (row, particle p of the chunk) in fragment order: tile mt =
+// row / 16 holds 64 lanes x 8 halves, lane = row % 16 + 16 (p / 8), half p % 8.
+__host__ __device__ inline int cs_idx(int row, int p)
 {
-    constexpr int RF = (3 * (NB + 1) * 2 + 1 + 3) / 4 * 4;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= N) return;
-    const int64_t i = feistel_inv((uint32_t)j, (uint32_t)N, h);
-    float r[RF];
-#pragma unroll
-    for (int e = 0; e < RF; ++e) r[e] = 0.f;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double t = frac(pos[d * N + j] * invL);
-#pragma unroll
-        for (int blk = 0; blk < NB; ++blk) {
-            double c, sn;
-            cis_turns(frac_mul(8 * blk, t), c, sn);
-            r[2 * (d * NB + blk)] = (float)c;
-            r[2 * (d * NB + blk) + 1] = (float)sn;
-        }
-        double c, sn;
-        cis_turns(t, c, sn);
-        r[2 * (3 * NB + d)] = (float)c;
-        r[2 * (3 * NB + d) + 1] = (float)sn;
-    }
-    r[6 * (NB + 1)] = (float)(q[j] * qfac);
-    float4 *o = reinterpret_cast<float4 *>(rec + i * RF);
-#pragma unroll
-    for (int e = 0; e < RF / 4; ++e) o[e] = make_float4(r[4 * e], r[4 * e + 1], r[4 * e + 2], r[4 * e + 3]);
+    return (row >> 4) * 512 + (p >> 3) * 128 + (row & 15) * 8 + (p & 7);
 }
 
-// LDS table layouts of the deposit.  Row strides are those of the largest
-// n_max of the tile class (8 MT), fixed at compile time, so that the
-// matrix-core waves address the 8 particles of their lane group with the
-// read instruction's immediate offset.  Row of particle p in the a table
-// (8 MT + 1 entries, k = 0..n used): groups of 8 particles separated by 4
-// float2, so the four lane groups (particles 8g..8g+7) start in different
-// banks.  b table (16 MT + 1 entries, k = -n..n used around column n): the
-// group padding of 8 float2 makes the groups' rows start 128 bytes apart
-// modulo the 256-byte bank cycle, so that lane groups 0/1 and 2/3, which read
-// 16 consecutive entries each in the same pass, use disjoint banks.  The CS
-// operand is stored in the matrix core's fragment order (cs_idx), so that a
-// lane's 16-byte fragment read is at 16 lane + const: 16-byte LDS reads run at
-// full rate only when the lanes' addresses are consecutive.  A table entry read as a volatile LDS double, which the compiler keeps as a
+// CS rows of the matrix-core operand: cos(n_z theta) for n_z = 1..n (rows
+// 0..n-1), sin(n_z theta) for n_z = 1..n (rows n..2n-1), zero padding to 16s.
+// The n_z = 0 row (all ones) is summed on the VALU instead.
+__host__ __device__ inline int mfma_cs_tiles(int n) { return (2 * n + 15) / 16; }
+// CS tiles per matrix-core wave: all of them up to 4 (n_max <= 32), else the
+// tiles are split over two waves that share the pairs.
+__host__ __device__ constexpr int dep_mtw(int MT) { return MT <= 4 ? MT : (MT + 1) / 2; }
+__host__ __device__ constexpr int dep_halves(int MT) { return MT <= 4 ? 1 : 2; }
+
+size_t dep_image_bytes(int n)
+{
+    switch (mfma_cs_tiles(n)) {
+    case 1: return DepTab<1>::bytes;
+    case 2: return DepTab<2>::bytes;
+    case 3: return DepTab<3>::bytes;
+    case 4: return DepTab<4>::bytes;
+    case 5: return DepTab<5>::bytes;
+    case 6: return DepTab<6>::bytes;
+    case 7: return DepTab<7>::bytes;
+    default: return DepTab<8>::bytes;
+    }
+}
+
+// One block of 4 waves per chunk image.  Tasks (axis d, block of 8 powers blk,
+// particle p), particle fastest: a wave takes 64 tasks at a time, a pair of
+// blocks of one axis (lanes 0-31 and 32-63), so its two half-waves never take
+// different branches.  Each task forms its anchor cis(2 pi 8 blk t_d) and step
+// cis(2 pi t_d) in FP64 and raises them to 8 powers by FP32 complex
+// multiplication; the anchor carries the factor its table needs (q' for X, the
+// running-sum sign and 7/8 for CS).  Slots past N hold q = 0.  cps: chunks per
+// particle split (the running-sum sign counts a split's own chunks).
+template <int MT>
+__global__ void __launch_bounds__(256)
+k_deposit_build(const double *__restrict__ pos, const double *__restrict__ q, int64_t N, int n,
+                double invL, int h, double qfac, int64_t cps, float *__restrict__ img)
+{
+    using T = DepTab<MT>;
+    __shared__ __align__(16) unsigned char sm[T::bytes];
+    _Float16 *hi = reinterpret_cast<_Float16 *>(sm);
+    _Float16 *lo = hi + T::cs_halves;
+    float2 *tx = reinterpret_cast<float2 *>(sm + T::x_off);
+    float2 *ty = reinterpret_cast<float2 *>(sm + T::y_off);
+    const int64_t chunk = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n1 = n + 1, nb = (n1 + 7) / 8, npair = (nb + 1) / 2;
+    for (int idx = tid; idx < (16 * MT - 2 * n) * kDepChunk; idx += 256) {
+        const int e = cs_idx(2 * n + idx / kDepChunk, idx % kDepChunk);
+        hi[e] = (_Float16)0.0f;
+        lo[e] = (_Float16)0.0f;
+    }
+    const int64_t cl = chunk - (chunk / cps) * cps;
+    const float csg = ((cl >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
+    const int p = lane & (kDepChunk - 1);
+    const int64_t s = chunk * kDepChunk + p;
+    int64_t j = -1;
+    if (s < N) j = feistel_fwd((uint32_t)s, (uint32_t)N, h);
+    for (int ws = wave; ws < 3 * npair; ws += 4) {
+        const int d = ws / npair;
+        const int blk = 2 * (ws - d * npair) + (lane >> 5);
+        if (blk >= nb) continue;
+        double t = 0.0, qq = 0.0;
+        if (j >= 0) {
+            t = frac(pos[d * N + j] * invL);
+            qq = q[j] * qfac;
+        }
+        double ac, as, c1d, s1d;
+        cis_turns(frac_mul(8 * blk, t), ac, as);
+        cis_turns(t, c1d, s1d);
+        const float c1 = (float)c1d, s1 = (float)s1d;
+        const int k0 = 8 * blk;
+        const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
+        if (d < 2) {
+            // X_k = q' cis(2 pi k t_x) or Y_k = cis(2 pi k t_y)
+            float uc = (float)(d == 0 ? qq * ac : ac), us = (float)(d == 0 ? qq * as : as);
+            float2 *dst = (d == 0 ? tx : ty) + p * T::sxy + k0;
+            for (int kk = 0; kk < kend; ++kk) {
+                dst[kk] = make_float2(uc, us);
+                const float tt = uc * c1 - us * s1;
+                us = uc * s1 + us * c1;
+                uc = tt;
+            }
+        } else {
+            float2_t v;
+            v[0] = csg * (float)ac;
+            v[1] = csg * (float)as;
+            for (int kk = 0; kk < kend; ++kk) {
+                const int k = k0 + kk;
+                if (k > 0) {
+                    // (cos, sin) split two at a time
+                    const half2_t hh = __builtin_convertvector(v, half2_t);
+                    const half2_t ll = split_lo2(v, hh);
+                    hi[cs_idx(k - 1, p)] = hh[0];
+                    lo[cs_idx(k - 1, p)] = ll[0];
+                    hi[cs_idx(n + k - 1, p)] = hh[1];
+                    lo[cs_idx(n + k - 1, p)] = ll[1];
+                }
+                const float tt = v[0] * c1 - v[1] * s1;
+                v[1] = v[0] * s1 + v[1] * c1;
+                v[0] = tt;
+            }
+        }
+    }
+    // X and Y entries past n (up to the compile-time stride) are never read
+    __syncthreads();
+    const float4 *src = reinterpret_cast<const float4 *>(sm);
+    float4 *dst = reinterpret_cast<float4 *>(img) + chunk * (int64_t)(T::bytes / 16);
+    for (int i = tid; i < (int)(T::bytes / 16); i += 256) dst[i] = src[i];
+}
+
+// The sum is taken in real form.  With X_u, Y_v the cos (u, v = 0) and sin
+// (1) tables of the x and y phases and Z_w those of z, the matrix core forms
+// the eight real sums T_uvw(k_x, k_y, n_z) = sum_j X_u(k_x) Y_v(k_y) Z_w(n_z)
+// over the block's particles for k_x, k_y = 0..n; every complex sum of the
+// half space follows by signs, since exp(-i a) = cos a - i sin a:
+//   P(k_x, +k_y, n_z) = T_ccc - T_ssc - i (T_scc + T_csc)
+//   P(k_x, -k_y, n_z) = T_ccc + T_ssc + i (T_csc - T_scc)
+// (P: w = c; Q, the sin(n_z) sums: w = s), which is the layout the
+// reduction reads.  The B operand of a (k_x, k_y) pair is then one product
+// per particle, X_u Y_v, formed and split into FP16 hi/lo by two
+// mixed-precision FMAs on the exact FP32 product.
+//
+// Block = kDepWaves matrix-core waves for one (row block, particle split)
+// pair; each wave owns 16 (k_x, k_y) pairs (one per lane of a 16-lane group)
+// and their four B tiles uv = cc, cs, sc, ss, and lane group g takes particles
+// 8g..8g+7 of a chunk.  The chunk images of the split stream into two LDS
+// buffers with direct global-to-LDS copies, the next chunk's in flight while
+// the current one is multiplied out; one barrier per chunk.  The n_z = 0 sums
+// (Z = 1) are accumulated on the VALU with one FMA per product.
+constexpr int kDepWaves = 12;
+constexpr int kDepThreads = 64 * kDepWaves;
+
+// XCD-aware block order: consecutive blocks go to different XCDs (each with
+// its own L2), so the grid is numbered such that the row blocks of one
+// particle split are dispatched to the same XCD one after another and their
+// reads of the split's chunk images hit that XCD's L2.  Linear block L runs on
+// XCD L % 8; its position t = L / 8 in that XCD's sequence selects row block
+// t % row_blocks of split (t / row_blocks) * 8 + L % 8.
+constexpr int kXcds = 8;
+
+// hi = fp16(a0 b0), fp16(a1 b1) packed; lo = fp16(a b - hi) each, with the
+// product formed exactly inside the mixed-precision FMA (FP32 inputs) and
+// rounded once.
+__device__ inline half2_t prod_hi2(float a0, float b0, float a1, float b1)
+{
+    half2_t hi;
+    asm("v_fma_mixlo_f16 %0, %1, %2, 0\n\t"
+        "v_fma_mixhi_f16 %0, %3, %4, 0"
+        : "=&v"(hi)
+        : "v"(a0), "v"(b0), "v"(a1), "v"(b1));
+    return hi;
+}
+__device__ inline half2_t prod_lo2(float a0, float b0, float a1, float b1, half2_t hi)
+{
+    half2_t lo;
+    asm("v_fma_mixlo_f16 %0, %1, %2, -%5 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %0, %3, %4, -%5 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "=&v"(lo)
+        : "v"(a0), "v"(b0), "v"(a1), "v"(b1), "v"(hi));
+    return lo;
+}
+
+// A table entry read as a volatile LDS double, which the compiler keeps as a
 // read of its own.
 typedef const volatile double __attribute__((address_space(3))) lds_f2;
 __device__ inline float2 lds_read(lds_f2 *p)
@@ -181,88 +326,34 @@ __device__ inline float2 lds_read(lds_f2 *p)
     return __builtin_bit_cast(float2, d);
 }
 
-template <int MT>
-struct DepTab {
-    static constexpr int wa = 8 * MT + 1;
-    static constexpr int wb = 16 * MT + 1;
-    static constexpr int pada = 4;
-    static constexpr int padb = 8;  // wb = 1 mod 4
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
 };
-__device__ inline int tab_row(int p, int w, int pad) { return p * w + (p >> 3) * pad; }
-// CS element (row, particle p of the chunk) in fragment order: tile mt =
-// row / 16 holds 64 lanes x 8 halves, lane = row % 16 + 16 (p / 8), half p % 8.
-__device__ inline int cs_idx(int row, int p)
-{
-    return (row >> 4) * 512 + (p >> 3) * 128 + (row & 15) * 8 + (p & 7);
-}
-
-// Running sums change sign every 2^kDepFlipLog chunks.
-constexpr int kDepFlipLog = 3;
-// FP32 sums of the n_z = 0 row are added into FP64 every 2^kDepDcLog chunks.
-constexpr int kDepDcLog = 4;
-
-// CS rows of the matrix-core operand: cos(n_z theta) for n_z = 1..n (rows
-// 0..n-1), sin(n_z theta) for n_z = 1..n (rows n..2n-1), zero padding to 16s.
-// The n_z = 0 row (all ones) is summed on the VALU instead.
-__host__ __device__ inline int mfma_cs_tiles(int n) { return (2 * n + 15) / 16; }
-
-template <int MT>
-__host__ __device__ constexpr size_t dep_buf_bytes()
-{
-    using T = DepTab<MT>;
-    return (size_t)MT * 16 * kDepChunk * 2 * sizeof(_Float16) +
-           (size_t)(kDepChunk * T::wa + 4 * T::pada + kDepChunk * T::wb + 4 * T::padb) * sizeof(float2);
-}
-
-// Block = kDepCompW matrix-core waves + kDepBuildW table-builder waves for
-// one (row block, particle split) pair; the split's particles are visited in
-// the pseudo-random order of the particle records, and the block's rows are
-// 16 NTW rows per matrix-core wave.
-// Per chunk of 32 particles the builder waves write the LDS tables of the
-// next chunk from the records: a = q cis(-k tx) for k = 0..n, b = cis(-k ty)
-// for k = -n..n (FP32), and the CS operand as FP16 hi/lo, while the
-// matrix-core waves multiply the current chunk out of the other buffer; one
-// barrier per chunk.  Each matrix-core lane forms its own H = a b fragment (8
-// particles x 1 row), splits it into hi/lo and adds its n_z = 0 contribution
-// on the VALU.
-constexpr int kDepCompW = 12;
-constexpr int kDepBuildW = 4;
-constexpr int kDepThreads = 64 * (kDepCompW + kDepBuildW);
-
-__host__ __device__ inline int dep_ntw(int MT) { return MT <= 4 ? 2 : 1; }
-__host__ __device__ inline int dep_rows_per_block(int MT) { return 16 * dep_ntw(MT) * kDepCompW; }
-
-// XCD-aware block order: consecutive blocks go to different XCDs (each with
-// its own L2), so the grid is numbered such that the row blocks of one
-// particle split are dispatched to the same XCD one after another and their
-// reads of the split's particle records hit that XCD's L2.  Linear block L
-// runs on XCD L % 8; its position t = L / 8 in that XCD's sequence selects
-// row block t % row_blocks of split (t / row_blocks) * 8 + L % 8.
-constexpr int kXcds = 8;
 
 template <int MT>
 __global__ void __launch_bounds__(kDepThreads)
-k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
+k_deposit_mfma(const float *__restrict__ img, int64_t N, int n, int lines, int Rpad,
                int64_t per_split, int row_blocks, int splits, double unscale_mf, double unscale_dc,
                float *__restrict__ part)
 {
+    using T = DepTab<MT>;
     const int blk_l = blockIdx.x;
     const int blk_t = blk_l / kXcds;
     const int rblk = blk_t % row_blocks;
     const int split = (blk_t / row_blocks) * kXcds + blk_l % kXcds;
     if (split >= splits) return;
-    constexpr int NTW = MT <= 4 ? 2 : 1;
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int n1 = n + 1;
-    constexpr int CSR = MT * 16;
-    constexpr size_t bufb = dep_buf_bytes<MT>();
-    using T = DepTab<MT>;
-    auto cs_hi = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb); };
-    auto cs_lo = [&](int b) { return reinterpret_cast<_Float16 *>(smem + b * bufb) + CSR * kDepChunk; };
-    auto tab_a = [&](int b) {
-        return reinterpret_cast<float2 *>(smem + b * bufb + (size_t)CSR * kDepChunk * 2 * sizeof(_Float16));
-    };
-    auto tab_b = [&](int b) { return tab_a(b) + kDepChunk * T::wa + 4 * T::pada; };
+    constexpr int MTW = dep_mtw(MT);
+    constexpr int NH = dep_halves(MT);
+    constexpr int SXY = T::sxy;
+    constexpr int PIECES = (int)(T::bytes / 1024);
+    // image buffers as separate static arrays: the copies into one never make
+    // the reads of the others wait.  Three where they fit in LDS beside the
+    // FP64 n_z = 0 sums (n_max <= 56), else two.
+    constexpr size_t kDcBytes = (size_t)kDepWaves * 4 * 64 * sizeof(double);
+    constexpr int NBUF = 3 * T::bytes + kDcBytes <= 160 * 1024 ? 3 : 2;
+    __shared__ half8 buf0[T::bytes / 16], buf1[T::bytes / 16], buf2[NBUF == 3 ? T::bytes / 16 : 1];
+    __shared__ double dcs[kDepWaves * 4 * 64];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -270,334 +361,223 @@ k_deposit_mfma(const float *__restrict__ rec, int64_t N, int n, int R, int Rpad,
     const int64_t j0 = (int64_t)split * per_split;
     const int64_t j1 = j0 + per_split < N ? j0 + per_split : N;
     const int64_t nchunks = (j1 - j0 + kDepChunk - 1) / kDepChunk;
-    const int nb = (n1 + 7) / 8;
+    const half8 *src = reinterpret_cast<const half8 *>(img) + (j0 / kDepChunk) * (int64_t)(T::bytes / 16);
+    auto stage = [&](int64_t c, half8 *dst) {
+        const half8 *sc = src + c * (int64_t)(T::bytes / 16);
+        for (int pc = wave; pc < PIECES; pc += kDepWaves)
+            __builtin_amdgcn_global_load_lds((const void *)(sc + 64 * pc + lane),
+                                             (__attribute__((address_space(3))) void *)(dst + 64 * pc),
+                                             16, 0, 0);
+    };
+    // images NBUF - 1 chunks ahead of the one being multiplied out
+    stage(0, buf0);
+    if (NBUF == 3 && nchunks > 1) stage(1, buf1);
 
-    for (int idx = tid; idx < (CSR - 2 * n) * kDepChunk; idx += kDepThreads)
-        for (int b = 0; b < 2; ++b) {
-            const int e = cs_idx(2 * n + idx / kDepChunk, idx % kDepChunk);
-            cs_hi(b)[e] = (_Float16)0.0f;
-            cs_lo(b)[e] = (_Float16)0.0f;
-        }
-
-    if (wave >= kDepCompW) {
-        // ---------------- table builders
-        // raised issue priority: the next chunk's tables are the critical path,
-        // the matrix-core waves fill the remaining issue slots
-        __builtin_amdgcn_s_setprio(2);
-        // tasks (axis d, block of 8 powers blk, particle p), particle fastest.
-        // A wave takes 64 tasks at a time, a pair of blocks of one axis (the
-        // block count is padded to even per axis), so its two half-waves never
-        // take different branches: wave slot ws = 4 sl + (builder wave) is
-        // axis ws / npair, block pair ws % npair.  The record fields of the
-        // next chunk's tasks are loaded one chunk ahead.
-        constexpr int kDepSlots = 6;  // enough for n_max <= 64
-        const int bw = wave - kDepCompW;
-        const int npair = (nb + 1) / 2;
-        const int rf = dep_rec_floats(n);
-        float rc[kDepSlots], rs[kDepSlots], sc[kDepSlots], ss[kDepSlots], rq[kDepSlots];
-        auto task_of = [&](int sl, int &d, int &blk, int &p) {
-            const int ws = sl * kDepBuildW + bw;
-            d = ws / npair;
-            blk = 2 * (ws - d * npair) + (lane >> 5);
-            p = lane & (kDepChunk - 1);
-            return d < 3 && blk < nb;
-        };
-        auto load_chunk = [&](int64_t c) {
-#pragma unroll
-            for (int sl = 0; sl < kDepSlots; ++sl) {
-                int d, blk, p;
-                const bool ok = task_of(sl, d, blk, p);
-                const int64_t j = j0 + c * kDepChunk + p;
-                rc[sl] = 1.f;
-                rs[sl] = 0.f;
-                sc[sl] = 1.f;
-                ss[sl] = 0.f;
-                rq[sl] = 0.f;
-                if (ok && c < nchunks && j < j1) {
-                    const float *r0 = rec + j * rf;
-                    rc[sl] = r0[2 * (d * nb + blk)];
-                    rs[sl] = r0[2 * (d * nb + blk) + 1];
-                    sc[sl] = r0[2 * (3 * nb + d)];
-                    ss[sl] = r0[2 * (3 * nb + d) + 1];
-                    rq[sl] = r0[6 * (nb + 1)];
-                }
-            }
-        };
-        // Powers by complex multiplication from the block's anchor; the anchor
-        // carries the factor each table needs (q and the conjugation for a, the
-        // running-sum sign and the 7/8 operand scale for CS), so the recurrence
-        // propagates it at no cost.
-        auto build_chunk = [&](int64_t c) {
-            const int b = (int)(c & 1);
-            const float csg = ((c >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
-#pragma unroll
-            for (int sl = 0; sl < kDepSlots; ++sl) {
-                int d, blk, p;
-                if (!task_of(sl, d, blk, p)) continue;
-                const float c1 = sc[sl], s1 = ss[sl];
-                const int k0 = 8 * blk;
-                const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
-                if (d == 0) {
-                    // u_k = q cis(-k tx): anchor q conj(cis), step conj(cis(tx))
-                    float uc = rq[sl] * rc[sl], us = -rq[sl] * rs[sl];
-                    float2 *dst = tab_a(b) + tab_row(p, T::wa, T::pada) + k0;
-                    for (int kk = 0; kk < kend; ++kk) {
-                        dst[kk] = make_float2(uc, us);
-                        const float t = uc * c1 + us * s1;
-                        us = us * c1 - uc * s1;
-                        uc = t;
-                    }
-                } else if (d == 1) {
-                    float fc = rc[sl], fs = rs[sl];
-                    float2 *dst = tab_b(b) + tab_row(p, T::wb, T::padb) + n;
-                    for (int kk = 0; kk < kend; ++kk) {
-                        const int k = k0 + kk;
-                        dst[k] = make_float2(fc, -fs);
-                        dst[-k] = make_float2(fc, fs);
-                        const float t = fc * c1 - fs * s1;
-                        fs = fc * s1 + fs * c1;
-                        fc = t;
-                    }
-                } else {
-                    float2_t v;
-                    v[0] = csg * rc[sl];
-                    v[1] = csg * rs[sl];
-                    _Float16 *hi = cs_hi(b), *lo = cs_lo(b);
-                    for (int kk = 0; kk < kend; ++kk) {
-                        const int k = k0 + kk;
-                        if (k > 0) {
-                            // (cos, sin) split two at a time
-                            const half2_t h = __builtin_convertvector(v, half2_t);
-                            const half2_t l = split_lo2(v, h);
-                            hi[cs_idx(k - 1, p)] = h[0];
-                            lo[cs_idx(k - 1, p)] = l[0];
-                            hi[cs_idx(n + k - 1, p)] = h[1];
-                            lo[cs_idx(n + k - 1, p)] = l[1];
-                        }
-                        const float t = v[0] * c1 - v[1] * s1;
-                        v[1] = v[0] * s1 + v[1] * c1;
-                        v[0] = t;
-                    }
-                }
-            }
-        };
-        load_chunk(0);
-        build_chunk(0);
-        load_chunk(1);
-        __syncthreads();
-        for (int64_t c = 0; c < nchunks; ++c) {
-            if (c + 1 < nchunks) {
-                build_chunk(c + 1);
-                load_chunk(c + 2);
-            }
-            __syncthreads();
-        }
-        return;
-    }
-
-    // ---------------- matrix-core waves
+    const int n1 = n + 1;
     const int g = lane >> 4;   // lane group: particles 8g..8g+7 of a chunk
-    const int ln = lane & 15;  // row within an N tile
-    const int row0 = rblk * dep_rows_per_block(MT) + wave * 16 * NTW;
-    int rnx[NTW], rnyo[NTW];
-    bool rok[NTW];
-#pragma unroll
-    for (int nt = 0; nt < NTW; ++nt) {
-        const int r = row0 + nt * 16 + ln;
-        rok[nt] = r < R;
-        int ny;
-        row_nxny(r < R ? r : R - 1, n, rnx[nt], ny);
-        rnyo[nt] = ny + n;  // column of k = ny in the b table
-    }
+    const int ln = lane & 15;  // pair within the wave
+    const int task = rblk * kDepWaves + wave;
+    const int pg = task / NH;                // group of 16 (k_x, k_y) pairs
+    const int mt0 = (task - pg * NH) * MTW;  // first CS tile of this wave
+    const int npairs = lines * n1;
+    const int pair = pg * 16 + ln;
+    const bool pok = pair < npairs;
+    const int pc = pok ? pair : npairs - 1;
+    const int kx = pc / n1, ky = pc - (pc / n1) * n1;
+    const bool idle = pg * 16 >= npairs;  // the last row block's spare waves
+    // Two of the three waves of each SIMD (waves 4..11) run a chunk behind in
+    // their vector work: they multiply out chunk c with the fragments formed
+    // during chunk c - 1 and then form those of chunk c + 1, so that waves in
+    // both orders share each SIMD (measured within 3% of one or three late
+    // waves per SIMD, and of none).
+    const bool late = NBUF == 3 && (wave >> 2) != 0;
 
-    f32x4 acc[MT][NTW][2];
+    f32x4 acc[MTW][4];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NTW; ++nt) acc[mt][nt][0] = acc[mt][nt][1] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // FP32 sums of the n_z = 0 row, added into this lane's FP64 slots in LDS
-    // (after the two table buffers) every 2^kDepDcLog chunks
-    float dc[NTW][2];
-    double *dcd = reinterpret_cast<double *>(smem + 2 * bufb) + (wave * NTW * 2) * 64 + lane;
+        for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // FP32 sums of the n_z = 0 row (tiles uv), added into this lane's FP64
+    // slots in LDS every 2^kDepDcLog chunks
+    float dc[4] = {0.f, 0.f, 0.f, 0.f};
+    double *dcd = dcs + (wave * 4) * 64 + lane;
 #pragma unroll
-    for (int nt = 0; nt < NTW; ++nt) {
-        dc[nt][0] = dc[nt][1] = 0.f;
-        dcd[(2 * nt) * 64] = 0.0;
-        dcd[(2 * nt + 1) * 64] = 0.0;
-    }
+    for (int t = 0; t < 4; ++t) dcd[t * 64] = 0.0;
+    const int xo = (8 * g) * SXY + kx;
+    const int yo = (8 * g) * SXY + ky;
+    // B fragments of the four tiles (8 particles x 1 pair per lane)
+    half8 bh[4], bl[4];
 
-    // lane bases of the a and b rows of particle 8 g of a chunk, column of the lane's row
-    int abase[NTW], bbase[NTW];
+    auto form = [&](const half8 *buf) {
+        const unsigned char *cb = reinterpret_cast<const unsigned char *>(buf);
+        lds_f2 *px = (lds_f2 *)(reinterpret_cast<const float2 *>(cb + T::x_off) + xo);
+        lds_f2 *py = (lds_f2 *)(reinterpret_cast<const float2 *>(cb + T::y_off) + yo);
 #pragma unroll
-    for (int nt = 0; nt < NTW; ++nt) {
-        abase[nt] = tab_row(8 * g, T::wa, T::pada) + rnx[nt];
-        bbase[nt] = tab_row(8 * g, T::wb, T::padb) + rnyo[nt];
-    }
-
-    __syncthreads();  // chunk 0's tables
-    if (row0 >= R) {
-        // every row of this wave lies past the last row (the last row block of a
-        // grid whose rows do not fill it): only the block's barriers remain
-        for (int64_t c = 0; c < nchunks; ++c) __syncthreads();
-        return;
-    }
-    // groups of 2^kDepFlipLog chunks; the running sums change sign between groups
-    for (int64_t c0 = 0; c0 < nchunks; c0 += (1 << kDepFlipLog)) {
-      const int64_t ce = c0 + (1 << kDepFlipLog) < nchunks ? c0 + (1 << kDepFlipLog) : nchunks;
-      for (int64_t c = c0; c < ce; ++c) {
-        const int b = (int)(c & 1);
-        const float2 *ta = tab_a(b), *tb = tab_b(b);
-        const _Float16 *chi = cs_hi(b), *clo = cs_lo(b);
-        // H fragments of every row tile first, then each CS tile read once
-        // and multiplied with all of them
-        half8 bre_h[NTW], bre_l[NTW], bim_h[NTW], bim_l[NTW];
+        for (int i = 0; i < 8; i += 2) {
+            const float2 x0 = lds_read(px + i * SXY);
+            const float2 y0 = lds_read(py + i * SXY);
+            const float2 x1 = lds_read(px + (i + 1) * SXY);
+            const float2 y1 = lds_read(py + (i + 1) * SXY);
 #pragma unroll
-        for (int nt = 0; nt < NTW; ++nt) {
-            float sre = 0.f, sim = 0.f;
-            // one 8-byte read per table entry: the compiler would otherwise pair
-            // the reads of two particles into one two-address read, whose halves
-            // fall in overlapping banks (the group padding is laid out for single
-            // reads) and which runs slower
-            lds_f2 *pa = (lds_f2 *)(ta + abase[nt]);
-            lds_f2 *pbt = (lds_f2 *)(tb + bbase[nt]);
-#pragma unroll
-            for (int i = 0; i < 8; i += 2) {
-                const float2 a0 = lds_read(pa + i * T::wa);
-                const float2 b0 = lds_read(pbt + i * T::wb);
-                const float2 a1 = lds_read(pa + (i + 1) * T::wa);
-                const float2 b1 = lds_read(pbt + (i + 1) * T::wb);
-                float2_t hr, hm;
-                hr[0] = a0.x * b0.x - a0.y * b0.y;
-                hm[0] = a0.x * b0.y + a0.y * b0.x;
-                hr[1] = a1.x * b1.x - a1.y * b1.y;
-                hm[1] = a1.x * b1.y + a1.y * b1.x;
-                sre += hr[0] + hr[1];
-                sim += hm[0] + hm[1];
-                const half2_t rh = __builtin_convertvector(hr, half2_t);
-                const half2_t mh = __builtin_convertvector(hm, half2_t);
-                const half2_t rl = split_lo2(hr, rh);
-                const half2_t ml = split_lo2(hm, mh);
-                bre_h[nt][i] = rh[0];
-                bre_h[nt][i + 1] = rh[1];
-                bre_l[nt][i] = rl[0];
-                bre_l[nt][i + 1] = rl[1];
-                bim_h[nt][i] = mh[0];
-                bim_h[nt][i + 1] = mh[1];
-                bim_l[nt][i] = ml[0];
-                bim_l[nt][i + 1] = ml[1];
+            for (int t = 0; t < 4; ++t) {
+                const float a0 = (t & 2) ? x0.y : x0.x, a1 = (t & 2) ? x1.y : x1.x;
+                const float b0 = (t & 1) ? y0.y : y0.x, b1 = (t & 1) ? y1.y : y1.x;
+                const half2_t hh = prod_hi2(a0, b0, a1, b1);
+                const half2_t ll = prod_lo2(a0, b0, a1, b1, hh);
+                bh[t][i] = hh[0];
+                bh[t][i + 1] = hh[1];
+                bl[t][i] = ll[0];
+                bl[t][i + 1] = ll[1];
+                dc[t] = __builtin_fmaf(a0, b0, dc[t]);
+                dc[t] = __builtin_fmaf(a1, b1, dc[t]);
             }
-            dc[nt][0] += sre;
-            dc[nt][1] += sim;
         }
+    };
+    auto multiply = [&](int64_t c, const half8 *buf) {
+        if (c > 0 && (c & ((1 << kDepFlipLog) - 1)) == 0) {
+            // the running sums change sign every 2^kDepFlipLog chunks
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const half8 ah = *reinterpret_cast<const half8 *>(&chi[(mt * 64 + lane) * 8]);
-            const half8 al = *reinterpret_cast<const half8 *>(&clo[(mt * 64 + lane) * 8]);
+            for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NTW; ++nt) {
-                acc[mt][nt][0] = mfma_split(ah, al, bre_h[nt], bre_l[nt], acc[mt][nt][0]);
-                acc[mt][nt][1] = mfma_split(ah, al, bim_h[nt], bim_l[nt], acc[mt][nt][1]);
-            }
+                for (int t = 0; t < 4; ++t) acc[mt][t] = -acc[mt][t];
+        }
+        const _Float16 *chi = reinterpret_cast<const _Float16 *>(buf);
+        const _Float16 *clo = chi + T::cs_halves;
+#pragma unroll
+        for (int mt = 0; mt < MTW; ++mt) {
+            if (NH > 1 && mt0 + mt >= MT) continue;  // wave-uniform
+            const half8 ah = *reinterpret_cast<const half8 *>(&chi[((mt0 + mt) * 64 + lane) * 8]);
+            const half8 al = *reinterpret_cast<const half8 *>(&clo[((mt0 + mt) * 64 + lane) * 8]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[mt][t] = mfma_split(ah, al, bh[t], bl[t], acc[mt][t]);
         }
         if ((c & ((1 << kDepDcLog) - 1)) == ((1 << kDepDcLog) - 1)) {
 #pragma unroll
-            for (int nt = 0; nt < NTW; ++nt) {
-                dcd[(2 * nt) * 64] += (double)dc[nt][0];
-                dcd[(2 * nt + 1) * 64] += (double)dc[nt][1];
-                dc[nt][0] = dc[nt][1] = 0.f;
+            for (int t = 0; t < 4; ++t) {
+                dcd[t * 64] += (double)dc[t];
+                dc[t] = 0.f;
             }
         }
-        __syncthreads();
-      }
-      if (ce < nchunks) {
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-              for (int nt = 0; nt < NTW; ++nt) {
-                  acc[mt][nt][0] = -acc[mt][nt][0];
-                  acc[mt][nt][1] = -acc[mt][nt][1];
-              }
-      }
-    }
+    };
+    // The chunk loop, one copy per role so that each is register-allocated on
+    // its own.  Chunk c from cur; nxt holds chunk c + 1, and chunk c + NBUF - 1
+    // goes into nx2.
+    auto run = [&](auto role) {
+        constexpr bool LATE = decltype(role)::value;
+        auto chunk = [&](int64_t c, const half8 *cur, const half8 *nxt, half8 *nx2) {
+            if (c + NBUF - 1 < nchunks) stage(c + NBUF - 1, nx2);
+            if (!idle) {
+                if constexpr (!LATE) {
+                    form(cur);
+                    multiply(c, cur);
+                } else {
+                    multiply(c, cur);
+                    if (c + 1 < nchunks) form(nxt);
+                }
+            }
+            __syncthreads();
+        };
+        __syncthreads();  // the first NBUF - 1 chunks
+        if (LATE && !idle) form(buf0);
+        if constexpr (NBUF == 3) {
+            // triples of chunks, so that each iteration names its buffers statically
+            for (int64_t c = 0; c < nchunks; c += 3) {
+                chunk(c, buf0, buf1, buf2);
+                if (c + 1 < nchunks) chunk(c + 1, buf1, buf2, buf0);
+                if (c + 2 < nchunks) chunk(c + 2, buf2, buf0, buf1);
+            }
+        } else {
+            for (int64_t c = 0; c < nchunks; c += 2) {
+                chunk(c, buf0, buf1, buf1);
+                if (c + 1 < nchunks) chunk(c + 1, buf1, buf0, buf0);
+            }
+        }
+    };
+    if (late)
+        run(BoolC<true>{});
+    else
+        run(BoolC<false>{});
+    if (idle) return;
 
     // after chunk c the running sums carry the sign (-1)^((c >> kDepFlipLog) & 1)
     const int64_t last = nchunks - 1;
     const double fsign = last >= 0 && ((last >> kDepFlipLog) & 1) ? -1.0 : 1.0;
     const double outscale = unscale_mf * fsign;
+    // the pair's rows of the row layout: (k_x, +k_y), and (k_x, -k_y) when
+    // both are non-zero (n_x = 0 rows with n_y < 0 lie in -H)
+    const int M = 2 * n + 1;
+    const int rp = kx == 0 ? ky : (n + 1) + (kx - 1) * M + (ky + n);
+    const int rm = (kx > 0 && ky > 0) ? (n + 1) + (kx - 1) * M + (n - ky) : -1;
     // FP32 partials (each already an FP32 sum; the splits are added in FP64)
     float *pb = part + (int64_t)split * (int64_t)n1 * 4 * Rpad;
+    // n_z = 0: the four lane groups' sums, added in a fixed order
+    double d[4];
 #pragma unroll
-    for (int nt = 0; nt < NTW; ++nt) {
-        // n_z = 0: the four lane groups' sums, added in a fixed order
-        double dre = dcd[(2 * nt) * 64] + (double)dc[nt][0], dim = dcd[(2 * nt + 1) * 64] + (double)dc[nt][1];
-        dre += __shfl_xor(dre, 16, 64);
-        dim += __shfl_xor(dim, 16, 64);
-        dre += __shfl_xor(dre, 32, 64);
-        dim += __shfl_xor(dim, 32, 64);
-        const int r = row0 + nt * 16 + ln;
-        if (!rok[nt]) continue;
-        if (g == 0) {
-            pb[0 * Rpad + r] = (float)(unscale_dc * dre);
-            pb[1 * (int64_t)Rpad + r] = (float)(unscale_dc * dim);
-            pb[2 * (int64_t)Rpad + r] = 0.f;
-            pb[3 * (int64_t)Rpad + r] = 0.f;
+    for (int t = 0; t < 4; ++t) {
+        d[t] = dcd[t * 64] + (double)dc[t];
+        d[t] += __shfl_xor(d[t], 16, 64);
+        d[t] += __shfl_xor(d[t], 32, 64);
+        d[t] *= unscale_dc;
+    }
+    if (!pok) return;
+    if (g == 0 && mt0 == 0) {
+        pb[0 * (int64_t)Rpad + rp] = (float)(d[0] - d[3]);
+        pb[1 * (int64_t)Rpad + rp] = (float)(-(d[2] + d[1]));
+        pb[2 * (int64_t)Rpad + rp] = 0.f;
+        pb[3 * (int64_t)Rpad + rp] = 0.f;
+        if (rm >= 0) {
+            pb[0 * (int64_t)Rpad + rm] = (float)(d[0] + d[3]);
+            pb[1 * (int64_t)Rpad + rm] = (float)(d[1] - d[2]);
+            pb[2 * (int64_t)Rpad + rm] = 0.f;
+            pb[3 * (int64_t)Rpad + rm] = 0.f;
         }
+    }
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
+    for (int mt = 0; mt < MTW; ++mt) {
+        if (NH > 1 && mt0 + mt >= MT) continue;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = mt * 16 + 4 * g + i;
-                int nz, slot;
-                if (m < n) {
-                    nz = m + 1;
-                    slot = 0;
-                } else if (m < 2 * n) {
-                    nz = m - n + 1;
-                    slot = 2;
-                } else {
-                    continue;
-                }
-                pb[((int64_t)nz * 4 + slot) * Rpad + r] = (float)(outscale * (double)acc[mt][nt][0][i]);
-                pb[((int64_t)nz * 4 + slot + 1) * Rpad + r] = (float)(outscale * (double)acc[mt][nt][1][i]);
+        for (int i = 0; i < 4; ++i) {
+            const int m = (mt0 + mt) * 16 + 4 * g + i;
+            int nz, slot;
+            if (m < n) {
+                nz = m + 1;
+                slot = 0;
+            } else if (m < 2 * n) {
+                nz = m - n + 1;
+                slot = 2;
+            } else {
+                continue;
+            }
+            const double cc = outscale * (double)acc[mt][0][i], cs = outscale * (double)acc[mt][1][i];
+            const double sc = outscale * (double)acc[mt][2][i], ss = outscale * (double)acc[mt][3][i];
+            float *o = pb + ((int64_t)nz * 4 + slot) * Rpad;
+            o[rp] = (float)(cc - ss);
+            o[Rpad + rp] = (float)(-(sc + cs));
+            if (rm >= 0) {
+                o[rm] = (float)(cc + ss);
+                o[Rpad + rm] = (float)(cs - sc);
             }
         }
     }
 }
 
-template <int MT>
-static constexpr size_t deposit_mfma_lds_mt()
-{
-    return 2 * dep_buf_bytes<MT>() + (size_t)kDepCompW * dep_ntw(MT) * 2 * 64 * sizeof(double);
-}
-
-size_t deposit_mfma_lds(int n)
-{
-    switch (mfma_cs_tiles(n)) {
-    case 1: return deposit_mfma_lds_mt<1>();
-    case 2: return deposit_mfma_lds_mt<2>();
-    case 3: return deposit_mfma_lds_mt<3>();
-    case 4: return deposit_mfma_lds_mt<4>();
-    case 5: return deposit_mfma_lds_mt<5>();
-    case 6: return deposit_mfma_lds_mt<6>();
-    case 7: return deposit_mfma_lds_mt<7>();
-    default: return deposit_mfma_lds_mt<8>();
-    }
-}
-
-// Particle splits: one block per (row block, split) holds a whole CU (16
-// waves, 96 KB of LDS at n_max = 32), so the grid runs in rounds of one block
-// per CU.  The split count is a multiple of kXcds (the XCD-aware numbering
-// needs whole groups) chosen to minimise rounds per particle, i.e. to avoid a
-// last round that is nearly empty; ties go to fewer splits (fewer partials).
-// A split holds at most kDepMaxRun particles: its matrix-core sums run in FP32
-// over the whole split, so their length is bounded whatever N is (more
-// particles mean more splits and FP64 cross-split sums instead).
+// Particle splits: one block per (row block, split) holds a whole CU, so the
+// grid runs in rounds of one block per CU.  The split count is a multiple of
+// kXcds (the XCD-aware numbering needs whole groups) chosen to minimise rounds
+// per particle, i.e. to avoid a last round that is nearly empty; ties go to
+// fewer splits (fewer partials).  A split holds at most kDepMaxRun particles:
+// its matrix-core sums run in FP32 over the whole split, so their length is
+// bounded whatever N is (more particles mean more splits and FP64 cross-split
+// sums instead).
 constexpr int64_t kDepMaxRun = 8192;
 MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
 {
     MfmaDepositPlan p;
-    const int rpb = dep_rows_per_block(mfma_cs_tiles(g.n));
-    p.row_blocks = (g.R + rpb - 1) / rpb;
+    // matrix-core wave tasks: groups of 16 (k_x, k_y) pairs, k_x on the
+    // context's n_x lines, times the CS halves
+    const int MT = mfma_cs_tiles(g.n);
+    const int tasks = (g.lines * g.n1 + 15) / 16 * dep_halves(MT);
+    p.row_blocks = (tasks + kDepWaves - 1) / kDepWaves;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -629,49 +609,42 @@ MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N)
 }
 
 template <int MT>
-static void launch_dep_mt(hipStream_t s, const float *rec, int64_t N, const Geom &g,
-                          const MfmaDepositPlan &pl, double unscale_mf, double unscale_dc,
-                          float *part)
+static void launch_dep_mt(hipStream_t s, const double *pos, const double *q, int64_t N, const Geom &g,
+                          double L, const MfmaDepositPlan &pl, double qfac, double unscale_mf,
+                          double unscale_dc, float *img, float *part)
 {
+    const int64_t chunks = (N + kDepChunk - 1) / kDepChunk;
+    hipLaunchKernelGGL(k_deposit_build<MT>, dim3((unsigned)chunks), dim3(256), 0, s, pos, q, N, g.n,
+                       1.0 / L, (int)pl.perm, qfac, pl.per_split / kDepChunk, img);
     // splits rounded up to whole groups of kXcds; blocks past the last split return
     const int groups = (pl.splits + kXcds - 1) / kXcds;
-    hipLaunchKernelGGL(k_deposit_mfma<MT>, dim3(groups * kXcds * pl.row_blocks), dim3(kDepThreads),
-                       deposit_mfma_lds(g.n), s, rec, N, g.n, g.R, g.Rpad, pl.per_split,
-                       pl.row_blocks, pl.splits, unscale_mf, unscale_dc, part);
+    hipLaunchKernelGGL(k_deposit_mfma<MT>, dim3(groups * kXcds * pl.row_blocks), dim3(kDepThreads), 0, s,
+                       img, N, g.n, g.lines, g.Rpad, pl.per_split, pl.row_blocks, pl.splits, unscale_mf,
+                       unscale_dc, part);
 }
 
-size_t deposit_mfma_rec_bytes(int64_t N, int n) { return (size_t)N * dep_rec_floats(n) * sizeof(float); }
+size_t deposit_mfma_rec_bytes(int64_t N, int n)
+{
+    return (size_t)((N + kDepChunk - 1) / kDepChunk) * dep_image_bytes(n);
+}
 
 hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q, int64_t N,
                                const Geom &g, double L, const MfmaDepositPlan &pl, double qscale,
                                float *rec, float *part)
 {
-    const dim3 pg((unsigned)((N + 255) / 256));
     const double qf = (double)kDepOpScale / qscale;
-    const int hp = (int)pl.perm;
-    switch ((g.n + 1 + 7) / 8) {
-    case 1: hipLaunchKernelGGL(k_deposit_prep<1>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
-    case 2: hipLaunchKernelGGL(k_deposit_prep<2>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
-    case 3: hipLaunchKernelGGL(k_deposit_prep<3>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
-    case 4: hipLaunchKernelGGL(k_deposit_prep<4>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
-    case 5: hipLaunchKernelGGL(k_deposit_prep<5>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
-    case 6: hipLaunchKernelGGL(k_deposit_prep<6>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
-    case 7: hipLaunchKernelGGL(k_deposit_prep<7>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
-    case 8: hipLaunchKernelGGL(k_deposit_prep<8>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
-    default: hipLaunchKernelGGL(k_deposit_prep<9>, pg, dim3(256), 0, s, pos, q, N, 1.0 / L, hp, qf, rec); break;
-    }
-    // H carries q / qscale scaled by 7/8, the CS operand another 7/8
+    // X carries q / qscale scaled by 7/8, the CS operand another 7/8
     const double unscale_dc = qscale / (double)kDepOpScale;
     const double unscale_mf = unscale_dc / (double)kDepOpScale;
     switch (mfma_cs_tiles(g.n)) {
-    case 1: launch_dep_mt<1>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
-    case 2: launch_dep_mt<2>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
-    case 3: launch_dep_mt<3>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
-    case 4: launch_dep_mt<4>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
-    case 5: launch_dep_mt<5>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
-    case 6: launch_dep_mt<6>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
-    case 7: launch_dep_mt<7>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
-    default: launch_dep_mt<8>(s, rec, N, g, pl, unscale_mf, unscale_dc, part); break;
+    case 1: launch_dep_mt<1>(s, pos, q, N, g, L, pl, qf, unscale_mf, unscale_dc, rec, part); break;
+    case 2: launch_dep_mt<2>(s, pos, q, N, g, L, pl, qf, unscale_mf, unscale_dc, rec, part); break;
+    case 3: launch_dep_mt<3>(s, pos, q, N, g, L, pl, qf, unscale_mf, unscale_dc, rec, part); break;
+    case 4: launch_dep_mt<4>(s, pos, q, N, g, L, pl, qf, unscale_mf, unscale_dc, rec, part); break;
+    case 5: launch_dep_mt<5>(s, pos, q, N, g, L, pl, qf, unscale_mf, unscale_dc, rec, part); break;
+    case 6: launch_dep_mt<6>(s, pos, q, N, g, L, pl, qf, unscale_mf, unscale_dc, rec, part); break;
+    case 7: launch_dep_mt<7>(s, pos, q, N, g, L, pl, qf, unscale_mf, unscale_dc, rec, part); break;
+    default: launch_dep_mt<8>(s, pos, q, N, g, L, pl, qf, unscale_mf, unscale_dc, rec, part); break;
     }
     return hipGetLastError();
 }

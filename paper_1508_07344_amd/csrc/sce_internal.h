@@ -110,7 +110,7 @@ hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const
 
 // ---- split-precision matrix-core path (kernels_mfma.hip)
 struct MfmaDepositPlan {
-    int row_blocks;     // ceil(R / 256)
+    int row_blocks;     // blocks of 12 matrix-core waves over the groups of 16 (k_x, k_y) pairs
     int splits;
     int64_t per_split;
     int64_t perm;       // half width h of the Feistel visiting order (2^(2h) >= N)

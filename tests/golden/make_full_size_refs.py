@@ -17,9 +17,9 @@ Cases (about an hour on 8 cores in total, most of it the first two):
                            Gaussian a = 0.01 (the timed workload), step 0.
 * ``random_plasma_65536_n16_kdk`` 65,536-particle neutral plasma, n_max = 16,
                            a = 0.02, dt = 1e-3: the oracle's own kick-drift-kick
-                           run, with the full state and the fields stored at
-                           steps 50 and 100 (the GPU is fed the oracle's state
-                           there, so both sides see identical positions).
+                           run, with the positions and the fields stored at
+                           steps 50 and 100 (the GPU is fed the oracle's
+                           positions there, so both sides see identical states).
 * ``two_species_262144_n16`` 262,144-particle ion/electron plasma, n_max = 16.
 * ``random_plasma_262144_n17`` 262,144 particles, n_max = 17.
 """
