@@ -49,10 +49,14 @@ def parse():
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=49152,
                     help="particles in the oracle's timed sample (all modes)")
-    ap.add_argument("--serve-requests", type=int, default=1024,
+    ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the serving workload (0 = skip the serving run)")
-    ap.add_argument("--serve-load", type=float, default=0.7,
-                    help="offered load as a fraction of the measured saturated capacity")
+    ap.add_argument("--serve-loads", default="0.5,0.7,0.9",
+                    help="offered loads, as fractions of the measured saturated capacity")
+    ap.add_argument("--serve-check", type=int, default=64,
+                    help="requests sampled for the per-request force error against FP64")
+    ap.add_argument("--peaks", type=int, default=1,
+                    help="measure the matrix-core and vector throughput peaks (libsce_peak.so)")
     ap.add_argument("--study", default="", choices=["", "longrun", "dispersion", "h2", "twod", "tent"],
                     help="run one validation study instead of the throughput benchmark")
     ap.add_argument("--long-steps", type=int, default=100000,
@@ -122,11 +126,35 @@ def measured_traffic(kernel):
     return float(m.group(1)) + float(m.group(2))
 
 
-def roofline(r, N):
+PEAK_PROBE = {"split_f16": "mfma_f16", "fp32": "fma_f32", "fp64": "fma_f64"}
+
+
+def measure_peaks():
+    """Sustained throughput of the three units the kernels are bound by, from
+    the probes of libsce_peak.so (TFLOP/s): dense FP16 matrix core, FP32 FMA
+    (no packed issue), FP64 FMA."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1508_07344_amd", "libsce_peak.so"))
+    out = {}
+    for name in ("mfma_f16", "fma_f32", "fma_f64"):
+        fn = getattr(lib, "sce_peak_" + name)
+        fn.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        fn.restype = ctypes.c_int
+        tf, ms = ctypes.c_double(), ctypes.c_double()
+        if fn(ctypes.byref(tf), ctypes.byref(ms)) != 0:
+            raise RuntimeError("peak probe failed: " + name)
+        out[name] = round(tf.value, 2)
+    return out
+
+
+def roofline(r, N, peaks=None):
     """Roofline of the dominant (longer) of the two particle x mode kernels.
     achieved = algorithmic flops per launch / average launch time, with the
     algorithmic count of complex multiply-adds: 8 flops per pair for the
-    deposit, 16 for the force."""
+    deposit, 16 for the force.  The split path's deposit time covers both of
+    its launches (the chunk-image build and the matrix-core kernel).  With
+    measured peaks, frac_measured is achieved over the probe's sustained rate
+    of the same unit."""
     pairs = N * r["modes_half"]
     mf = r["precision"] == "split_f16"
     peak = PEAK_TFLOPS[r["precision"]]
@@ -136,20 +164,29 @@ def roofline(r, N):
     dom = max(kern, key=lambda k: kern[k][1])
     other = "force" if dom == "deposit" else "deposit"
     traffic = measured_traffic(kern[dom][0]) if mf else None
-    return {"bound": BOUND[r["precision"]], "kernel": kern[dom][0],
-            "achieved": round(rates[dom], 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(rates[dom] / peak, 4), "traffic": traffic,
-            "other_kernel": {"kernel": kern[other][0], "achieved": round(rates[other], 3),
-                             "frac": round(rates[other] / peak, 4)}}
+    out = {"bound": BOUND[r["precision"]], "kernel": kern[dom][0],
+           "achieved": round(rates[dom], 3), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(rates[dom] / peak, 4), "traffic": traffic,
+           "other_kernel": {"kernel": kern[other][0], "achieved": round(rates[other], 3),
+                            "frac": round(rates[other] / peak, 4)}}
+    if peaks:
+        pm = peaks[PEAK_PROBE[r["precision"]]]
+        out["peak_measured"] = pm
+        out["frac_measured"] = round(rates[dom] / pm, 4)
+        out["other_kernel"]["frac_measured"] = round(rates[other] / pm, 4)
+    return out
 
 
-def _drive(srv, reqs, t_arrive):
+def _drive(srv, reqs, t_arrive, label=""):
     """Submit each request at its arrival time (seconds from now) and tick until
-    every request has finished.  Returns wall seconds and the server's ids."""
+    every request has finished.  Returns wall seconds and the server's ids.
+    Prints a progress line to stderr every 10 s of wall time."""
     order = sorted(range(len(reqs)), key=lambda i: t_arrive[i])
     ids = {}
     t0 = time.perf_counter()
+    t_print = t0
     k = 0
+    done = 0
     while True:
         now = time.perf_counter() - t0
         while k < len(order) and t_arrive[order[k]] <= now:
@@ -157,6 +194,10 @@ def _drive(srv, reqs, t_arrive):
             ids[srv.sce_server_submit(reqs[i].particles)] = i
             k += 1
         na, nq = srv.sce_server_tick()
+        if label and time.perf_counter() - t_print > 10.0:
+            t_print = time.perf_counter()
+            print(f"serving {label}: {t_print - t0:.0f} s, submitted {k}/{len(reqs)}, "
+                  f"active {na}, queued {nq}", file=sys.stderr, flush=True)
         if na == 0 and nq == 0:
             if k == len(order):
                 break
@@ -164,11 +205,24 @@ def _drive(srv, reqs, t_arrive):
     return time.perf_counter() - t0, ids
 
 
-def serving(sce, n_requests, load):
+def _e_F(F, ref):
+    import numpy as np
+    return float(np.max(np.linalg.norm(F - ref, axis=0)) / max(np.max(np.linalg.norm(ref, axis=0)), 1e-300))
+
+
+def serving(sce, n_requests, loads, n_check):
     """Serving workload: independent requests (N log-uniform in [2, 8192], n_max
     in {4, 8, 16}, steps log-uniform in [100, 10^4]) with Poisson arrivals at
-    ``load`` x the saturated capacity measured first on the same mix."""
+    each offered load x the saturated capacity, which is measured first on the
+    same mix.  Per load: throughput, per-step latency (wall time of the tick
+    that carried it, and the device time of the tick's kernels alone),
+    admission wait, per-request energy change and the force error of sampled
+    requests at completion against an FP64 context at their final state.  Once:
+    the force error at admission against the FP64 oracle (the sampled requests
+    run for zero steps), and the request with the largest energy change run
+    again in FP64."""
     import numpy as np
+    import oracle
     import workloads
 
     def half(n):
@@ -177,55 +231,96 @@ def serving(sce, n_requests, load):
     # saturated capacity: 256 requests of the same mix (steps / 10) submitted at once
     cal = workloads.serving_requests(n_requests=256, steps_range=(10, 1000), salt=1)
     with sce.Server(hbm_budget_bytes=16 << 30, precision="fp32") as srv:
-        _drive(srv, cal, [0.0] * len(cal))
+        _drive(srv, cal, [0.0] * len(cal), "capacity")
         st = srv.sce_server_stats()
     capacity = st["pairs"] / st["busy_s"]
+    print(f"serving capacity {capacity:.3e} pairs/s", file=sys.stderr, flush=True)
 
-    # unit-rate Poisson arrivals, rescaled to ``rate`` (the draws do not depend on the rate)
+    # unit-rate Poisson arrivals, rescaled per load (the draws do not depend on the rate)
     reqs = workloads.serving_requests(n_requests=n_requests, rate_per_s=1.0)
     work = np.array([r.particles.N * half(r.particles.n_max) * (r.particles.n_steps + 1) for r in reqs],
                     dtype=np.float64)
-    rate = load * capacity / float(np.mean(work))
-    t_arrive = [r.arrival_s / rate for r in reqs]
+    check = set(range(0, n_requests, max(1, n_requests // n_check)))
+    rows, worst = [], None
+    for load in loads:
+        rate = load * capacity / float(np.mean(work))
+        t_arrive = [r.arrival_s / rate for r in reqs]
+        with sce.Server(hbm_budget_bytes=16 << 30, precision="fp32") as srv:
+            wall, ids = _drive(srv, reqs, t_arrive, f"load {load}")
+            st = srv.sce_server_stats()
+            done = srv.sce_server_poll(len(reqs) + 1)
+            drift, errs = [], []
+            for rid in done:
+                x, v, F, d0, d1 = srv.sce_server_result(rid)
+                i = ids[rid]
+                drift.append(abs(d1.total - d0.total) / abs(d0.total))
+                if worst is None or drift[-1] > worst[0]:
+                    worst = (drift[-1], i, load)
+                if i in check:
+                    p = reqs[i].particles
+                    with sce.Context(p.L, p.n_max, p.shape, p.a) as c:
+                        c.sce_set_options(p.eps0, "fp64", "kdk")
+                        c.sce_set_particles(np.ascontiguousarray(x), np.ascontiguousarray(v),
+                                            np.ascontiguousarray(p.q), np.ascontiguousarray(p.m))
+                        errs.append(_e_F(F, c.sce_force()))
+        rows.append({
+            "offered_load": load,
+            "arrival_rate_per_s": rate,
+            "wall_s": wall,
+            "pairs_per_s": st["pairs"] / wall,
+            "request_steps_per_s": st["request_steps"] / wall,
+            "p50_step_ms": 1e3 * st["p50_step_s"],
+            "p99_step_ms": 1e3 * st["p99_step_s"],
+            "max_step_ms": 1e3 * st["max_step_s"],
+            "gpu_p50_step_ms": 1e3 * st["gpu_p50_step_s"],
+            "gpu_p99_step_ms": 1e3 * st["gpu_p99_step_s"],
+            "p50_wait_ms": 1e3 * st["p50_wait_s"],
+            "p99_wait_ms": 1e3 * st["p99_wait_s"],
+            "requests": int(st["requests_done"]),
+            "hbm_peak_bytes": st["hbm_peak_bytes"],
+            "energy_drift_rel_p50": float(np.median(drift)),
+            "energy_drift_rel_max": float(np.max(drift)),
+            "e_F_completion_vs_fp64_max": float(np.max(errs)),
+        })
+        print(f"serving load {load} done: " + json.dumps(rows[-1]), file=sys.stderr, flush=True)
+
+    # force error at admission: the sampled requests run zero steps (one pass
+    # at their initial positions) through the server, against the oracle
+    sub = [reqs[i] for i in sorted(check)]
+    adm = []
     with sce.Server(hbm_budget_bytes=16 << 30, precision="fp32") as srv:
-        wall, ids = _drive(srv, reqs, t_arrive)
-        st = srv.sce_server_stats()
-        done = srv.sce_server_poll(len(reqs) + 1)
-        drift, errs = [], []
-        sample = set(done[:: max(1, len(done) // 16)])
-        for rid in done:
+        rid_of = {srv.sce_server_submit(r.particles, n_steps=0): r for r in sub}
+        while True:
+            na, nq = srv.sce_server_tick()
+            if na == 0 and nq == 0:
+                break
+        for rid in srv.sce_server_poll(len(sub) + 1):
             x, v, F, d0, d1 = srv.sce_server_result(rid)
-            drift.append(abs(d1.total - d0.total) / abs(d0.total))
-            if rid in sample:
-                p = reqs[ids[rid]].particles
-                with sce.Context(p.L, p.n_max, p.shape, p.a) as c:
-                    c.sce_set_options(p.eps0, "fp64", "kdk")
-                    c.sce_set_particles(np.ascontiguousarray(x), np.ascontiguousarray(v),
-                                        np.ascontiguousarray(p.q), np.ascontiguousarray(p.m))
-                    Fr = c.sce_force()
-                errs.append(float(np.max(np.linalg.norm(F - Fr, axis=0)) /
-                                  max(np.max(np.linalg.norm(Fr, axis=0)), 1e-300)))
+            p = rid_of[rid].particles
+            ref = oracle.fields(p.positions(), p.q, p.L, p.n_max, p.shape, p.a, p.eps0)
+            if p.N > 1:
+                adm.append(_e_F(F, ref.F))
+    # the largest energy change, run again in FP64
+    drift64 = None
+    p = reqs[worst[1]].particles
+    with sce.Server(hbm_budget_bytes=4 << 30, precision="fp64") as srv:
+        rid = srv.sce_server_submit(p)
+        while True:
+            na, nq = srv.sce_server_tick()
+            if na == 0 and nq == 0:
+                break
+        x, v, F, d0, d1 = srv.sce_server_result(rid)
+        drift64 = abs(d1.total - d0.total) / abs(d0.total)
     return {
         "workload": f"{n_requests} requests, N log-uniform [2, 8192], n_max in {{4, 8, 16}}, "
                     "steps log-uniform [100, 1e4], Gaussian a = 0.05, dt = 1e-3, Poisson arrivals",
         "precision": "fp32",
-        "offered_load": load,
         "capacity_pairs_per_s": capacity,
-        "arrival_rate_per_s": rate,
-        "wall_s": wall,
-        "pairs_per_s": st["pairs"] / wall,
-        "request_steps_per_s": st["request_steps"] / wall,
-        "p50_step_ms": 1e3 * st["p50_step_s"],
-        "p99_step_ms": 1e3 * st["p99_step_s"],
-        "max_step_ms": 1e3 * st["max_step_s"],
-        "p50_wait_ms": 1e3 * st["p50_wait_s"],
-        "p99_wait_ms": 1e3 * st["p99_wait_s"],
-        "requests": int(st["requests_done"]),
-        "hbm_peak_bytes": st["hbm_peak_bytes"],
-        "energy_drift_rel_p50": float(np.median(drift)),
-        "energy_drift_rel_max": float(np.max(drift)),
-        "e_F_vs_fp64_max": float(np.max(errs)),
-        "e_F_sampled_requests": len(errs),
+        "loads": rows,
+        "e_F_admission_vs_oracle_max": float(np.max(adm)),
+        "e_F_sampled_requests": len(check),
+        "worst_energy_change": {"N": p.N, "n_max": p.n_max, "steps": p.n_steps, "load": worst[2],
+                                "fp32": worst[0], "fp64": drift64},
     }
 
 
@@ -487,21 +582,52 @@ def study_tent(sce, steps, warmup, precisions):
                         "vs cold_lattice_128x128x64_n32 (delta field, Gaussian a = 0.01)"}
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p, sample):
+    """The FP64 oracle on the host: one deposit and one force pass of a sample
+    of the particles against all modes, on every thread it uses by default and
+    on one thread (a smaller sample; the rate of a direct double loop does not
+    depend on the sample size)."""
     import numpy as np
     import oracle
-    idx = np.arange(0, p.N, max(1, p.N // sample))[:sample]
-    sub = p.subset(idx)
     modes = oracle.half_modes(p.n_max)
-    t0 = time.perf_counter()
-    rho = oracle.deposit(sub.positions(), sub.q, p.L, modes, p.shape, p.a)
-    ps = oracle.psi(rho, p.L, modes, p.eps0, p.shape, p.a)
-    oracle.force_from_psi(sub.positions(), sub.q, p.L, modes, ps)
-    t = time.perf_counter() - t0
-    pairs = len(idx) * len(modes)
-    return {"value": pairs / t, "unit": "pairs/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{len(idx)} of {p.N} particles x all {len(modes)} half-space modes, "
-                      f"one deposit + one force pass ({t:.1f} s)"}
+
+    def one(n):
+        idx = np.arange(0, p.N, max(1, p.N // n))[:n]
+        sub = p.subset(idx)
+        t0 = time.perf_counter()
+        rho = oracle.deposit(sub.positions(), sub.q, p.L, modes, p.shape, p.a)
+        ps = oracle.psi(rho, p.L, modes, p.eps0, p.shape, p.a)
+        oracle.force_from_psi(sub.positions(), sub.q, p.L, modes, ps)
+        t = time.perf_counter() - t0
+        return len(idx) * len(modes) / t, len(idx), t
+
+    threads = oracle.threads()
+    rate, n_all, t_all = one(sample)
+    oracle.set_threads(1)
+    try:
+        rate1, n_one, t_one = one(max(64, sample // max(threads, 1)))
+    finally:
+        oracle.set_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"value": rate, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_all} of {p.N} particles x all {len(modes)} half-space modes, "
+                      f"one deposit + one force pass ({t_all:.1f} s)",
+            "value_1core": rate1,
+            "sample_1core": f"{n_one} particles x all modes, one deposit + one force pass ({t_one:.1f} s)",
+            "nproc": os.cpu_count(), "affinity_cpus": affinity, "cpu_model": _cpu_model()}
 
 
 def main():
@@ -541,10 +667,14 @@ def main():
         return
     p = workloads.cold_lattice()
     main_r = time_path(sce, p, a.precision, a.steps, a.warmup)
+    print(f"timed {a.precision}: {main_r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     variants = {}
     for prec in [x for x in a.also.split(",") if x and x != a.precision]:
         variants[prec] = time_path(sce, p, prec, a.steps, a.warmup)
-        variants[prec]["roofline"] = roofline(variants[prec], p.N)
+        print(f"timed {prec}: {variants[prec]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    peaks = measure_peaks() if a.peaks else None
+    for prec in variants:
+        variants[prec]["roofline"] = roofline(variants[prec], p.N, peaks)
     line = {
         "metric": METRIC,
         "value": main_r["pairs_per_s"],
@@ -561,12 +691,15 @@ def main():
         "config": {"workload": "cold_lattice_128x128x64_n32", "N": p.N, "n_max": p.n_max,
                    "modes_half": main_r["modes_half"], "shape": "gaussian", "a": p.a,
                    "dt": p.dt, "scheme": "kdk", "precision": a.precision},
-        "roofline": roofline(main_r, p.N),
+        "roofline": roofline(main_r, p.N, peaks),
         "detail": {k: v for k, v in main_r.items() if k not in ("precision",)},
         "variants": variants,
     }
+    if peaks:
+        line["peaks_measured_tflops"] = peaks
     if a.serve_requests:
-        line["serving"] = serving(sce, a.serve_requests, a.serve_load)
+        line["serving"] = serving(sce, a.serve_requests,
+                                  [float(x) for x in a.serve_loads.split(",") if x], a.serve_check)
     if a.cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, a.cpu_sample)
     print(json.dumps(line), flush=True)

@@ -334,6 +334,10 @@ typedef struct {
     double p50_wait_s, p99_wait_s;              /* admission wait: submit to the start of the
                                                    first tick that carried the request */
     double hbm_used_bytes, hbm_peak_bytes;      /* arena bytes held by resident requests */
+    double gpu_p50_step_s, gpu_p99_step_s;      /* per request-pass device time of the tick's
+                                                   kernels alone (HIP events around its
+                                                   launches), weighted like p50/p99_step_s:
+                                                   the rest of a step's latency is the host's */
 } sce_server_report;
 
 /* Create a server on the current HIP device.  opts may be NULL (defaults).

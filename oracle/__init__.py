@@ -109,6 +109,8 @@ def _load():
             lib.sce_oracle_field_energy_2d.restype = f64
             lib.sce_oracle_threads.argtypes = []
             lib.sce_oracle_threads.restype = i32
+            lib.sce_oracle_set_threads.argtypes = [i32]
+            lib.sce_oracle_set_threads.restype = None
             _lib = lib
     return _lib
 
@@ -124,6 +126,11 @@ def _f64(a) -> np.ndarray:
 def threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(_load().sce_oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads for the oracle's OpenMP loops (results do not depend on it)."""
+    _load().sce_oracle_set_threads(int(n))
 
 
 def half_modes(n_max: int, dim: int = 3) -> np.ndarray:

@@ -346,3 +346,16 @@ int32_t sce_oracle_threads(void)
     }
     return n;
 }
+
+/* Set the number of threads of the parallel loops above (the CPU baseline's
+ * one-core and all-core runs); n < 1 is ignored.  The results do not depend on
+ * it: each output's sum runs serially in index order. */
+void sce_oracle_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -44,8 +44,13 @@ def _run(cmd):
             sys.stderr.write(line + "\n")
 
 
+PEAK_SOURCE = "peak_probe.hip"
+PEAK_LIB = os.path.join(HERE, "libsce_peak.so")
+
+
 def build(verbose: bool = False) -> str:
-    """Compile every source and link libsce.so (always rebuilds)."""
+    """Compile every source and link libsce.so and the throughput probes'
+    libsce_peak.so (always rebuilds)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     objs, cmds = [], []
     for src in SOURCES:
@@ -54,11 +59,14 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
         if verbose:
             print(" ".join(cmds[-1]))
+    ptmp = PEAK_LIB + ".tmp%d" % os.getpid()
+    cmds.append([HIPCC, *COMMON_FLAGS, "-shared", os.path.join(CSRC, PEAK_SOURCE), "-o", ptmp])
     # one hipcc per source, in parallel (each is single-threaded)
     jobs = max(1, min(len(cmds), os.cpu_count() or 1, 16))
     with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
         for f in [ex.submit(_run, c) for c in cmds]:
             f.result()
+    os.replace(ptmp, PEAK_LIB)
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     _run(cmd)

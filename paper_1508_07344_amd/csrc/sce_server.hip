@@ -185,6 +185,8 @@ struct sce_server_s {
 
     // statistics
     std::vector<std::pair<double, int>> tick_lat;  // (seconds, resident requests)
+    std::vector<std::pair<double, int>> tick_gpu;  // device time of the tick's kernels
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
     std::vector<double> waits;
     int64_t ticks = 0, request_steps = 0, requests_done = 0;
     double busy = 0.0, pairs = 0.0;
@@ -480,6 +482,8 @@ sce_status sce_server_create(const sce_server_opts *opts, sce_server *out)
             s->own_stream = e == hipSuccess;
         }
     }
+    if (e == hipSuccess) e = hipEventCreate(&s->ev_a);
+    if (e == hipSuccess) e = hipEventCreate(&s->ev_b);
     if (e == hipSuccess) e = hipMalloc(&s->arena, s->arena_bytes);
     if (e == hipSuccess) e = s->desc.reserve((size_t)s->max_slots);
     if (e != hipSuccess) {
@@ -568,11 +572,15 @@ sce_status sce_server_tick(sce_server s, int32_t *n_active, int32_t *n_queued)
         std::vector<Request *> fin;
         st = stage_finishing(s, fin);
         if (st != SCE_OK) return st;
+        SHIP(s, hipEventRecord(s->ev_a, s->stream));
         st = launch_tick(s);
         if (st != SCE_OK) return st;
+        SHIP(s, hipEventRecord(s->ev_b, s->stream));
         st = copy_finishing(s, fin);
         if (st != SCE_OK) return st;
         SHIP(s, hipStreamSynchronize(s->stream));
+        float gpu_ms = 0.f;
+        SHIP(s, hipEventElapsedTime(&gpu_ms, s->ev_a, s->ev_b));
         const int na = (int)s->active.size();
         double pr = 0.0;
         for (auto &r : s->active) {
@@ -588,6 +596,7 @@ sce_status sce_server_tick(sce_server s, int32_t *n_active, int32_t *n_queued)
         retire(s, fin);
         const double dt = now_s() - t0;
         s->tick_lat.emplace_back(dt, na);
+        s->tick_gpu.emplace_back(1e-3 * (double)gpu_ms, na);
         ++s->ticks;
         s->request_steps += na;
         s->busy += dt;
@@ -640,6 +649,8 @@ sce_status sce_server_stats(sce_server s, sce_server_report *o)
     o->p50_step_s = weighted_pct(s->tick_lat, 0.50);
     o->p99_step_s = weighted_pct(s->tick_lat, 0.99);
     for (auto &e : s->tick_lat) o->max_step_s = std::max(o->max_step_s, e.first);
+    o->gpu_p50_step_s = weighted_pct(s->tick_gpu, 0.50);
+    o->gpu_p99_step_s = weighted_pct(s->tick_gpu, 0.99);
     std::vector<std::pair<double, int>> w;
     for (double x : s->waits) w.emplace_back(x, 1);
     o->p50_wait_s = weighted_pct(w, 0.50);
@@ -657,6 +668,8 @@ void sce_server_destroy(sce_server s)
     (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     drop_graph(s);
+    if (s->ev_a) (void)hipEventDestroy(s->ev_a);
+    if (s->ev_b) (void)hipEventDestroy(s->ev_b);
     s->desc.release();
     s->dep.release();
     s->red.release();

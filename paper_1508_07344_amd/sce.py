@@ -60,7 +60,8 @@ class _ServerReport(ctypes.Structure):
                 ("p50_step_s", ctypes.c_double), ("p99_step_s", ctypes.c_double),
                 ("max_step_s", ctypes.c_double), ("p50_wait_s", ctypes.c_double),
                 ("p99_wait_s", ctypes.c_double), ("hbm_used_bytes", ctypes.c_double),
-                ("hbm_peak_bytes", ctypes.c_double)]
+                ("hbm_peak_bytes", ctypes.c_double), ("gpu_p50_step_s", ctypes.c_double),
+                ("gpu_p99_step_s", ctypes.c_double)]
 
 
 @dataclasses.dataclass

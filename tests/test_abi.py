@@ -23,12 +23,28 @@ def test_header_declares_the_api():
     for required in ("sce_create", "sce_create_2d", "sce_create_tent", "sce_field_shape",
                      "sce_dimension", "sce_set_step_graph", "sce_set_small_step", "sce_set_options", "sce_set_particles", "sce_get_particles",
                      "sce_mode_count", "sce_modes", "sce_deposit", "sce_psi", "sce_force",
+                     "sce_force_noalloc",
                      "sce_step", "sce_diagnostics", "sce_get_state", "sce_set_state", "sce_sync",
                      "sce_timing_enable", "sce_timing_read", "sce_destroy", "sce_status_string",
                      "sce_last_error", "sce_server_create", "sce_server_submit", "sce_server_tick",
                      "sce_server_poll", "sce_server_result", "sce_server_stats",
                      "sce_server_last_error", "sce_server_destroy"):
         assert required in names
+
+
+def test_peak_probe_library_exports_its_header():
+    """libsce_peak.so (the roofline denominators' throughput probes) exports
+    every function include/sce_peak.h declares."""
+    lib = os.path.join(ROOT, "paper_1508_07344_amd", "libsce_peak.so")
+    if not os.path.exists(lib):
+        pytest.skip("libsce_peak.so not built")
+    hdr = open(os.path.join(ROOT, "include", "sce_peak.h")).read()
+    declared = set(re.findall(r"^\s*int\s+(sce_peak_\w+)\s*\(", hdr, re.M))
+    assert declared == {"sce_peak_mfma_f16", "sce_peak_fma_f32", "sce_peak_fma_f64"}
+    out = subprocess.run(["nm", "-D", "--defined-only", lib], capture_output=True, text=True,
+                         check=True).stdout
+    assert declared <= set(re.findall(r"\bT (sce_peak_\w+)", out))
+    ctypes.CDLL(lib)
 
 
 def test_library_exports_every_declared_symbol():

@@ -14,7 +14,7 @@ Cases:
   4,096 sampled particles, every precision.
 * the 65,536-particle plasma at the oracle's own steps 50 and 100: both sides
   take the oracle's positions there, so the fields are compared at identical
-  states (a chaotic run's trajectories separate within a few plasma periods).
+  states; the GPU's own FP64 trajectory is compared with the oracle's too.
 * two dimensions above the small-count kernels, where the force visits only
   the n_x = 0 line of rows.
 
