@@ -194,6 +194,7 @@ k_deposit_build(const double *__restrict__ pos, const double *__restrict__ q, in
 {
     using T = DepTab<MT>;
     __shared__ __align__(16) unsigned char sm[T::bytes];
+    __shared__ double tsl[3][kDepChunk], qsl[kDepChunk];
     _Float16 *hi = reinterpret_cast<_Float16 *>(sm);
     _Float16 *lo = hi + T::cs_halves;
     float2 *tx = reinterpret_cast<float2 *>(sm + T::x_off);
@@ -208,19 +209,27 @@ k_deposit_build(const double *__restrict__ pos, const double *__restrict__ q, in
     }
     const int64_t cl = chunk - (chunk / cps) * cps;
     const float csg = ((cl >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
+    // one thread per (slot, axis) gathers its particle's coordinate and leaves
+    // its turns t = frac(x / L) and q' in LDS for the tasks
+    if (tid < 3 * kDepChunk) {
+        const int d = tid / kDepChunk, sl = tid - d * kDepChunk;
+        const int64_t s = chunk * kDepChunk + sl;
+        double t = 0.0, qq = 0.0;
+        if (s < N) {
+            const int64_t j = feistel_fwd((uint32_t)s, (uint32_t)N, h);
+            t = frac(pos[d * N + j] * invL);
+            if (d == 0) qq = q[j] * qfac;
+        }
+        tsl[d][sl] = t;
+        if (d == 0) qsl[sl] = qq;
+    }
+    __syncthreads();
     const int p = lane & (kDepChunk - 1);
-    const int64_t s = chunk * kDepChunk + p;
-    int64_t j = -1;
-    if (s < N) j = feistel_fwd((uint32_t)s, (uint32_t)N, h);
     for (int ws = wave; ws < 3 * npair; ws += 4) {
         const int d = ws / npair;
         const int blk = 2 * (ws - d * npair) + (lane >> 5);
         if (blk >= nb) continue;
-        double t = 0.0, qq = 0.0;
-        if (j >= 0) {
-            t = frac(pos[d * N + j] * invL);
-            qq = q[j] * qfac;
-        }
+        const double t = tsl[d][p], qq = qsl[p];
         double ac, as, c1d, s1d;
         cis_turns(frac_mul(8 * blk, t), ac, as);
         cis_turns(t, c1d, s1d);
@@ -709,55 +718,23 @@ __host__ __device__ inline int force_row(int pr, int n, const ForceQuads &f, int
 // kept within the normal FP32 range, and no smaller than 2^-60 |psi(r, 0)| so
 // that psi / s stays far from overflow.  Records are stored interleaved,
 // rinfo[2 pr] = A, rinfo[2 pr + 1] = B, for 4 Qpad padded rows.
-__global__ void __launch_bounds__(256)
-k_force_rows(const float *__restrict__ ftab, const float *__restrict__ psi0, int n, int lines,
-             int nzp, float4 *__restrict__ rinfo)
-{
-    // one wave per padded row: the row's table entries read by the 64 lanes
-    // together, their largest magnitude by a butterfly
-    const ForceQuads f = force_quads(n, lines);
-    const int pr = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (pr >= 4 * f.Qpad) return;
-    int nx = 0, ny = 0;
-    const int r = force_row(pr, n, f, nx, ny);
-    if (r < 0) {
-        if (lane == 0) {
-            rinfo[2 * pr] = make_float4(0.f, 0.f, 0.f, 0.f);
-            rinfo[2 * pr + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        return;
-    }
-    float m = 0.f;
-    const float *fr = ftab + (int64_t)r * nzp * 8;
-    for (int i = lane; i < n * 8; i += 64) m = fmaxf(m, fabsf(fr[i]));
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-    if (lane != 0) return;
-    const float pre = psi0[2 * r], pim = psi0[2 * r + 1];
-    m = fmaxf(m, ldexpf(fmaxf(fabsf(pre), fabsf(pim)), -60));
-    int e = 0;
-    if (m > 0.f) {
-        frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
-        e = e < -126 ? -126 : (e > 126 ? 126 : e);
-    }
-    const float s = m > 0.f ? ldexpf(1.0f, e) : 1.0f;
-    const float inv = m > 0.f ? ldexpf(1.0f, -e) : 1.0f;
-    rinfo[2 * pr] = make_float4(pre * inv, pim * inv, 0.f, 0.f);
-    rinfo[2 * pr + 1] = make_float4((float)nx * s, (float)ny * s, s, 0.f);
-}
-
+//
 // W fragments: wf[t][s][h][lane][8] halves, t = quad (< Qpad), s = K step, h = hi/lo.
 // Lane l, element i: A row m = l % 16 -> padded row 4t + m/4, component
 // e = m % 4; K index k = 32 s + 8 (l/16) + i -> cos (k < nzk) or sin of
 // n_z = (k mod nzk) + 1.
+// One wave per (quad, K step): the 16 lanes of each of the quad's four rows
+// (m / 4 fixed) first find the row's scale together, reading the whole row
+// (all K steps), then each lane packs its 8 entries; the K step 0 wave writes
+// the row records.
 __global__ void __launch_bounds__(256)
-k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, int n, int lines,
-             int nzp, int nzk, int ks, _Float16 *__restrict__ wf)
+k_force_pack(const float *__restrict__ ftab, const float *__restrict__ psi0, int n, int lines,
+             int nzp, int nzk, int ks, float4 *__restrict__ rinfo, _Float16 *__restrict__ wf)
 {
     const ForceQuads f = force_quads(n, lines);
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t total = (int64_t)f.Qpad * ks * 64;
-    if (gid >= total) return;
+    if (gid >= total) return;  // whole waves: total is a multiple of 64
     const int lane = (int)(gid & 63);
     const int64_t ts = gid >> 6;
     const int s = (int)(ts % ks);
@@ -765,9 +742,35 @@ k_force_pack(const float *__restrict__ ftab, const float4 *__restrict__ rinfo, i
     const int mrow = lane & 15;
     const int pr = 4 * t + (mrow >> 2);
     const int e = mrow & 3;
-    int nx, ny;
+    int nx = 0, ny = 0;
     const int r = force_row(pr, n, f, nx, ny);
-    const float inv = r >= 0 ? 1.0f / rinfo[2 * pr + 1].z : 1.0f;
+    // the row's largest |entry|: lane (e, lane group g) reads entries e + 4 g + 16 j
+    float mx = 0.f;
+    if (r >= 0) {
+        const float *fr = ftab + (int64_t)r * nzp * 8;
+        for (int i = e + 4 * (lane >> 4); i < n * 8; i += 16) mx = fmaxf(mx, fabsf(fr[i]));
+    }
+    for (int o = 1; o <= 32; o <<= 1)
+        if (o != 4 && o != 8) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    float inv = 1.0f;
+    if (r >= 0) {
+        const float pre = psi0[2 * r], pim = psi0[2 * r + 1];
+        mx = fmaxf(mx, ldexpf(fmaxf(fabsf(pre), fabsf(pim)), -60));
+        int ex = 0;
+        if (mx > 0.f) {
+            frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+            ex = ex < -126 ? -126 : (ex > 126 ? 126 : ex);
+        }
+        const float sc = mx > 0.f ? ldexpf(1.0f, ex) : 1.0f;
+        inv = mx > 0.f ? ldexpf(1.0f, -ex) : 1.0f;
+        if (s == 0 && e == 0 && lane < 16) {
+            rinfo[2 * pr] = make_float4(pre * inv, pim * inv, 0.f, 0.f);
+            rinfo[2 * pr + 1] = make_float4((float)nx * sc, (float)ny * sc, sc, 0.f);
+        }
+    } else if (s == 0 && e == 0 && lane < 16) {
+        rinfo[2 * pr] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rinfo[2 * pr + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     _Float16 hi[8], lo[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -801,13 +804,11 @@ hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0
                              float4 *rinfo, _Float16 *wf)
 {
     const ForceQuads f = force_quads(g.n, g.lines);
-    hipLaunchKernelGGL(k_force_rows, dim3((unsigned)f.Qpad), dim3(256), 0, s, ftab, psi0, g.n,
-                       g.lines, g.nzp, rinfo);
     const int nzk = (g.n + 15) / 16 * 16;
     const int ks = nzk / 16;
     const int64_t total = (int64_t)f.Qpad * ks * 64;
     hipLaunchKernelGGL(k_force_pack, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ftab,
-                       rinfo, g.n, g.lines, g.nzp, nzk, ks, wf);
+                       psi0, g.n, g.lines, g.nzp, nzk, ks, rinfo, wf);
     return hipGetLastError();
 }
 

@@ -117,8 +117,8 @@ struct MfmaDepositPlan {
 };
 MfmaDepositPlan plan_deposit_mfma(const Geom &g, int64_t N);
 // Deposit partial sums (layout of launch_deposit, in FP32).  rec: scratch of
-// deposit_mfma_rec_bytes(N) for the per-particle records in visiting order;
-// charges enter scaled by 1/qscale and the partials leave scaled back.
+// deposit_mfma_rec_bytes(N) for the chunk images in visiting order; charges
+// enter scaled by 1/qscale and the partials leave scaled back.
 size_t deposit_mfma_rec_bytes(int64_t N, int n);
 hipError_t launch_deposit_mfma(hipStream_t s, const double *pos, const double *q, int64_t N,
                                const Geom &g, double L, const MfmaDepositPlan &pl, double qscale,
