@@ -108,19 +108,30 @@ def time_path(sce, p, precision, steps, warmup):
     return out
 
 
+def code_hash(path):
+    """First 16 hex digits of the SHA-256 of a source file's code: the text
+    with // comments removed and runs of white space collapsed, so that an
+    edit of comments alone keeps the hash."""
+    import hashlib
+    import re
+    txt = open(path, encoding="utf-8").read()
+    txt = re.sub(r"//[^\n]*", "", txt)
+    txt = " ".join(txt.split())
+    return hashlib.sha256(txt.encode()).hexdigest()[:16]
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of a matrix-core kernel from the committed rocprofv3
-    summary, or None if the kernel source changed since it was measured."""
-    import hashlib
+    summary, or None if the kernel code changed since it was measured."""
     import re
     src = os.path.join(ROOT, "paper_1508_07344_amd", "csrc", "kernels_mfma.hip")
     summ = os.path.join(ROOT, "profiles", "traffic_cold_lattice_1M_n32.md")
     try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = code_hash(src)
         txt = open(summ).read()
     except OSError:
         return None
-    m = re.search(r"traffic kernel=%s fetch_bytes=(\S+) write_bytes=(\S+) source_sha256_16=(\w+)" % kernel, txt)
+    m = re.search(r"traffic kernel=%s fetch_bytes=(\S+) write_bytes=(\S+) code_sha256_16=(\w+)" % kernel, txt)
     if not m or m.group(3) != sha:
         return None
     return float(m.group(1)) + float(m.group(2))

@@ -35,7 +35,9 @@ retained modes W_self = (sum q^2 / (eps0 V)) sum_H S^2 / |k|^2.
 Parity: all functions here are pinned by ``tests/test_oracle_pins.py`` (FFT
 special case, Ewald alpha-independence, rock-salt Madelung constant, gradient,
 adjointness, conservation laws, reversibility, h^2 energy error, cold-plasma
-dispersion).
+dispersion), the two-dimensional ones also by ``tests/test_oracle_pins_2d.py``,
+and ``self_energy`` by ``tests/test_oracle_pins_self.py`` (a lone particle's
+field energy; the grid mean of a pair's).
 """
 from __future__ import annotations
 

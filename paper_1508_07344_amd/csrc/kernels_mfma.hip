@@ -289,10 +289,11 @@ k_deposit_build(const double *__restrict__ pos, const double *__restrict__ q, in
 // Block = kDepWaves matrix-core waves for one (row block, particle split)
 // pair; each wave owns 16 (k_x, k_y) pairs (one per lane of a 16-lane group)
 // and their four B tiles uv = cc, cs, sc, ss, and lane group g takes particles
-// 8g..8g+7 of a chunk.  The chunk images of the split stream into two LDS
-// buffers with direct global-to-LDS copies, the next chunk's in flight while
-// the current one is multiplied out; one barrier per chunk.  The n_z = 0 sums
-// (Z = 1) are accumulated on the VALU with one FMA per product.
+// 8g..8g+7 of a chunk.  The chunk images of the split stream into a ring of
+// LDS buffers (three where they fit, else two) with direct global-to-LDS
+// copies, the later chunks' in flight while the current one is multiplied
+// out; one barrier per chunk.  The n_z = 0 sums (Z = 1) are accumulated on the
+// VALU with one FMA per product.
 constexpr int kDepWaves = 12;
 constexpr int kDepThreads = 64 * kDepWaves;
 
