@@ -38,19 +38,12 @@ __device__ inline void split_f16(float x, _Float16 &hi, _Float16 &lo)
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef float float2_t __attribute__((ext_vector_type(2)));
 
-// lo parts of two values whose hi parts (round to nearest) are packed in hi:
-// lo = fp16(x - hi), the difference formed exactly inside the mixed-precision
-// FMA and rounded once, as fp16(x - (float)hi) is (that difference is exact in
-// FP32).  Two instructions instead of two conversions back, two subtractions
-// and a packing conversion.
+// lo parts of two values x whose hi parts (round to nearest) are packed in
+// hi: lo = fp16(x - hi), x - hi being exact in FP32.
 __device__ inline half2_t split_lo2(float2_t x, half2_t hi)
 {
-    half2_t lo;
-    asm("v_fma_mixlo_f16 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]\n\t"
-        "v_fma_mixhi_f16 %0, -%1, 1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
-        : "=&v"(lo)
-        : "v"(hi), "v"(x[0]), "v"(x[1]));
-    return lo;
+    const float2_t d = {x[0] - (float)hi[0], x[1] - (float)hi[1]};
+    return __builtin_convertvector(d, half2_t);
 }
 
 __device__ inline f32x4 mfma16(half8 a, half8 b, f32x4 c)
@@ -182,11 +175,12 @@ size_t dep_image_bytes(int n)
 // One block of 4 waves per chunk image.  Tasks (axis d, block of 8 powers blk,
 // particle p), particle fastest: a wave takes 64 tasks at a time, a pair of
 // blocks of one axis (lanes 0-31 and 32-63), so its two half-waves never take
-// different branches.  Each task forms its anchor cis(2 pi 8 blk t_d) and step
-// cis(2 pi t_d) in FP64 and raises them to 8 powers by FP32 complex
-// multiplication; the anchor carries the factor its table needs (q' for X, the
-// running-sum sign and 7/8 for CS).  Slots past N hold q = 0.  cps: chunks per
-// particle split (the running-sum sign counts a split's own chunks).
+// different branches.  Each task takes its anchor cis(2 pi 8 blk t_d) (FP64)
+// and step cis(2 pi t_d), formed once per particle and axis, and raises them
+// to 8 powers by FP32 complex multiplication; the anchor carries the factor
+// its table needs (q' for X, the running-sum sign and 7/8 for CS).  Slots past
+// N hold q = 0.  cps: chunks per particle split (the running-sum sign counts a
+// split's own chunks).
 template <int MT>
 __global__ void __launch_bounds__(256)
 k_deposit_build(const double *__restrict__ pos, const double *__restrict__ q, int64_t N, int n,
@@ -194,7 +188,12 @@ k_deposit_build(const double *__restrict__ pos, const double *__restrict__ q, in
 {
     using T = DepTab<MT>;
     __shared__ __align__(16) unsigned char sm[T::bytes];
-    __shared__ double tsl[3][kDepChunk], qsl[kDepChunk];
+    // per (axis, slot): the anchors cis(2 pi 8 b t) of the blocks of 8 powers
+    // and the one-step factor cis(2 pi t)
+    constexpr int NBMAX = MT + 1;
+    __shared__ double2 anc[3][kDepChunk][NBMAX];
+    __shared__ float2 stp[3][kDepChunk];
+    __shared__ double qsl[kDepChunk];
     _Float16 *hi = reinterpret_cast<_Float16 *>(sm);
     _Float16 *lo = hi + T::cs_halves;
     float2 *tx = reinterpret_cast<float2 *>(sm + T::x_off);
@@ -209,8 +208,10 @@ k_deposit_build(const double *__restrict__ pos, const double *__restrict__ q, in
     }
     const int64_t cl = chunk - (chunk / cps) * cps;
     const float csg = ((cl >> kDepFlipLog) & 1) ? -kDepOpScale : kDepOpScale;
-    // one thread per (slot, axis) gathers its particle's coordinate and leaves
-    // its turns t = frac(x / L) and q' in LDS for the tasks
+    // One thread per (slot, axis) gathers its particle's coordinate, forms
+    // e = cis(2 pi t) of its turns t = frac(x / L) (one FP64 sincos), e^8 by
+    // three FP64 squarings and the anchors (e^8)^b by FP64 products, and
+    // leaves them with q' in LDS for the tasks.
     if (tid < 3 * kDepChunk) {
         const int d = tid / kDepChunk, sl = tid - d * kDepChunk;
         const int64_t s = chunk * kDepChunk + sl;
@@ -220,7 +221,23 @@ k_deposit_build(const double *__restrict__ pos, const double *__restrict__ q, in
             t = frac(pos[d * N + j] * invL);
             if (d == 0) qq = q[j] * qfac;
         }
-        tsl[d][sl] = t;
+        double ec, es;
+        cis_turns(t, ec, es);
+        stp[d][sl] = make_float2((float)ec, (float)es);
+        double e8c = ec, e8s = es;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const double c2 = e8c * e8c - e8s * e8s;
+            e8s = 2.0 * e8c * e8s;
+            e8c = c2;
+        }
+        double ac = 1.0, as = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            anc[d][sl][b] = make_double2(ac, as);
+            const double c2 = ac * e8c - as * e8s;
+            as = ac * e8s + as * e8c;
+            ac = c2;
+        }
         if (d == 0) qsl[sl] = qq;
     }
     __syncthreads();
@@ -229,11 +246,11 @@ k_deposit_build(const double *__restrict__ pos, const double *__restrict__ q, in
         const int d = ws / npair;
         const int blk = 2 * (ws - d * npair) + (lane >> 5);
         if (blk >= nb) continue;
-        const double t = tsl[d][p], qq = qsl[p];
-        double ac, as, c1d, s1d;
-        cis_turns(frac_mul(8 * blk, t), ac, as);
-        cis_turns(t, c1d, s1d);
-        const float c1 = (float)c1d, s1 = (float)s1d;
+        const double qq = qsl[p];
+        const double2 an = anc[d][p][blk];
+        const double ac = an.x, as = an.y;
+        const float2 st = stp[d][p];
+        const float c1 = st.x, s1 = st.y;
         const int k0 = 8 * blk;
         const int kend = n1 - k0 < 8 ? n1 - k0 : 8;
         if (d < 2) {
@@ -304,28 +321,6 @@ constexpr int kDepThreads = 64 * kDepWaves;
 // XCD L % 8; its position t = L / 8 in that XCD's sequence selects row block
 // t % row_blocks of split (t / row_blocks) * 8 + L % 8.
 constexpr int kXcds = 8;
-
-// hi = fp16(a0 b0), fp16(a1 b1) packed; lo = fp16(a b - hi) each, with the
-// product formed exactly inside the mixed-precision FMA (FP32 inputs) and
-// rounded once.
-__device__ inline half2_t prod_hi2(float a0, float b0, float a1, float b1)
-{
-    half2_t hi;
-    asm("v_fma_mixlo_f16 %0, %1, %2, 0\n\t"
-        "v_fma_mixhi_f16 %0, %3, %4, 0"
-        : "=&v"(hi)
-        : "v"(a0), "v"(b0), "v"(a1), "v"(b1));
-    return hi;
-}
-__device__ inline half2_t prod_lo2(float a0, float b0, float a1, float b1, half2_t hi)
-{
-    half2_t lo;
-    asm("v_fma_mixlo_f16 %0, %1, %2, -%5 op_sel_hi:[0,0,1]\n\t"
-        "v_fma_mixhi_f16 %0, %3, %4, -%5 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
-        : "=&v"(lo)
-        : "v"(a0), "v"(b0), "v"(a1), "v"(b1), "v"(hi));
-    return lo;
-}
 
 // A table entry read as a volatile LDS double, which the compiler keeps as a
 // read of its own.
@@ -432,14 +427,19 @@ k_deposit_mfma(const float *__restrict__ img, int64_t N, int n, int lines, int R
             for (int t = 0; t < 4; ++t) {
                 const float a0 = (t & 2) ? x0.y : x0.x, a1 = (t & 2) ? x1.y : x1.x;
                 const float b0 = (t & 1) ? y0.y : y0.x, b1 = (t & 1) ? y1.y : y1.x;
-                const half2_t hh = prod_hi2(a0, b0, a1, b1);
-                const half2_t ll = prod_lo2(a0, b0, a1, b1, hh);
+                // p = fp32(a b), hi = fp16(p) and lo = fp16(a b - hi), the
+                // difference formed in FP32 (exactly, up to the product's
+                // own rounding); two values per packed conversion
+                const float2_t pv = {a0 * b0, a1 * b1};
+                const half2_t hh = __builtin_convertvector(pv, half2_t);
+                const float2_t lv = {pv[0] - (float)hh[0], pv[1] - (float)hh[1]};
+                const half2_t ll = __builtin_convertvector(lv, half2_t);
                 bh[t][i] = hh[0];
                 bh[t][i + 1] = hh[1];
                 bl[t][i] = ll[0];
                 bl[t][i + 1] = ll[1];
-                dc[t] = __builtin_fmaf(a0, b0, dc[t]);
-                dc[t] = __builtin_fmaf(a1, b1, dc[t]);
+                dc[t] += pv[0];
+                dc[t] += pv[1];
             }
         }
     };
