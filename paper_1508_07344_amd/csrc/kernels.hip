@@ -403,6 +403,7 @@ __device__ inline double block_max(double v, double *sh)
 // cell and all splits in one loop left most compute units idle at n_max = 16
 // (37 blocks) while the loop streamed the partials.
 constexpr int kReduceWays = 8;
+constexpr int kReduceUnroll = 4;
 
 template <typename T, typename P>
 __global__ void __launch_bounds__(64 * kReduceWays)
@@ -424,7 +425,30 @@ k_reduce_solve(const P *__restrict__ part, int splits, int n, int R, int Rpad, i
             const int row = (int)(cell - (int64_t)nz * R);
             const int64_t sstride = (int64_t)n1 * 4 * Rpad;
             const P *pp = part + (int64_t)way * sstride + (int64_t)nz * 4 * Rpad + row;
-            for (int sp = way; sp < splits; sp += kReduceWays, pp += kReduceWays * sstride) {
+            // kReduceUnroll splits' values are loaded before any is added, so
+            // their loads are in flight together; the additions keep the
+            // split order
+            int sp = way;
+            for (; sp + (kReduceUnroll - 1) * kReduceWays < splits;
+                 sp += kReduceUnroll * kReduceWays, pp += kReduceUnroll * kReduceWays * sstride) {
+                P v[kReduceUnroll][4];
+#pragma unroll
+                for (int u = 0; u < kReduceUnroll; ++u) {
+                    const P *qq = pp + (int64_t)u * kReduceWays * sstride;
+                    v[u][0] = qq[0];
+                    v[u][1] = qq[Rpad];
+                    v[u][2] = qq[2 * (int64_t)Rpad];
+                    v[u][3] = qq[3 * (int64_t)Rpad];
+                }
+#pragma unroll
+                for (int u = 0; u < kReduceUnroll; ++u) {
+                    Pr += (double)v[u][0];
+                    Pi += (double)v[u][1];
+                    Qr += (double)v[u][2];
+                    Qi += (double)v[u][3];
+                }
+            }
+            for (; sp < splits; sp += kReduceWays, pp += kReduceWays * sstride) {
                 Pr += (double)pp[0];
                 Pi += (double)pp[Rpad];
                 Qr += (double)pp[2 * (int64_t)Rpad];
@@ -918,13 +942,6 @@ hipError_t launch_force(hipStream_t s, const double *pos, const double *q, const
 }
 
 // ------------------------------------------------------------------ drift / kick
-__device__ inline double wrap_box(double x, double L, double invL)
-{
-    double w = x - L * floor(x * invL);
-    if (w >= L || w < 0.0) w = 0.0;
-    return w;
-}
-
 __global__ void __launch_bounds__(256)
 k_kick_drift(double *__restrict__ pos, double *__restrict__ vel, const double *__restrict__ F,
              const double *__restrict__ m, int64_t N, double L, double invL, double a, double b,

@@ -863,10 +863,10 @@ __device__ inline void stage_w(const half8 *__restrict__ src, half8 *dst, int np
 // without spills.  KS = 3, 4 need more than 128 VGPRs and run 2 waves per SIMD.
 template <int KS, bool PHI>
 __global__ void __launch_bounds__(64 * kForceWaves, KS <= 2 ? 4 : 2)
-k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
+k_force_mfma(double *__restrict__ pos, const double *__restrict__ q,
              const double *__restrict__ m, double *__restrict__ vel, const _Float16 *__restrict__ wf,
-             const float4 *__restrict__ rinfo, int n, int lines, double invL, int64_t N, double kick,
-             double *__restrict__ F, double *__restrict__ phi)
+             const float4 *__restrict__ rinfo, int n, int lines, double L, double invL, int64_t N,
+             double kick, Drift nd, double *__restrict__ F, double *__restrict__ phi)
 {
     constexpr int NT = kForceNT;
     constexpr int kForceTM = force_tm<KS>();
@@ -1061,36 +1061,57 @@ k_force_mfma(const double *__restrict__ pos, const double *__restrict__ q,
                 vel[N + j] += a * Fy;
                 vel[2 * N + j] += a * Fz;
             }
+            if (nd.kick != 0.0 || nd.drift != 0.0) {
+                // the next step's first half kick and drift, as a separate
+                // kick-drift pass would apply them (same operations in the
+                // same order); this thread is the only one that reads x_j
+                const double am = nd.kick != 0.0 ? nd.kick / m[j] : 0.0;
+                const double Fd[3] = {Fx, Fy, Fz};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    double v = vel[d * N + j];
+                    if (nd.kick != 0.0) {
+                        v += am * Fd[d];
+                        vel[d * N + j] = v;
+                    }
+                    if (nd.drift != 0.0) {
+                        const double x = pos[d * N + j] + nd.drift * v;
+                        pos[d * N + j] = nd.wrap ? wrap_box(x, L, invL) : x;
+                    }
+                }
+            }
         }
     }
 }
 
 template <int KS>
-static void launch_force_ks(hipStream_t s, dim3 grid, dim3 block, const double *pos, const double *q,
+static void launch_force_ks(hipStream_t s, dim3 grid, dim3 block, double *pos, const double *q,
                             const double *m, double *vel, const _Float16 *wf, const float4 *rinfo,
-                            int n, int lines, double invL, int64_t N, double kick, double *F,
-                            double *phi)
+                            int n, int lines, double L, int64_t N, double kick, const Drift &nd,
+                            double *F, double *phi)
 {
     if (phi)
         hipLaunchKernelGGL((k_force_mfma<KS, true>), grid, block, 0, s, pos, q, m, vel, wf, rinfo, n,
-                           lines, invL, N, kick, F, phi);
+                           lines, L, 1.0 / L, N, kick, nd, F, phi);
     else
         hipLaunchKernelGGL((k_force_mfma<KS, false>), grid, block, 0, s, pos, q, m, vel, wf, rinfo, n,
-                           lines, invL, N, kick, F, phi);
+                           lines, L, 1.0 / L, N, kick, nd, F, phi);
 }
 
-hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, const double *m,
+hipError_t launch_force_mfma(hipStream_t s, double *pos, const double *q, const double *m,
                              double *vel, const _Float16 *wf, const float4 *rinfo, const Geom &g,
-                             double L, int64_t N, double kick, double *F, double *phi)
+                             double L, int64_t N, double kick, const Drift &nd, double *F,
+                             double *phi)
 {
+    if ((nd.kick != 0.0 || nd.drift != 0.0) && !F) return hipErrorInvalidValue;
     const int ks = (g.n + 15) / 16;
     const int64_t blocks = (N + kForceBlockParticles - 1) / kForceBlockParticles;
     const dim3 grid((unsigned)blocks), block(64 * kForceWaves);
     switch (ks) {
-    case 1: launch_force_ks<1>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, 1.0 / L, N, kick, F, phi); break;
-    case 2: launch_force_ks<2>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, 1.0 / L, N, kick, F, phi); break;
-    case 3: launch_force_ks<3>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, 1.0 / L, N, kick, F, phi); break;
-    default: launch_force_ks<4>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, 1.0 / L, N, kick, F, phi); break;
+    case 1: launch_force_ks<1>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, L, N, kick, nd, F, phi); break;
+    case 2: launch_force_ks<2>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, L, N, kick, nd, F, phi); break;
+    case 3: launch_force_ks<3>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, L, N, kick, nd, F, phi); break;
+    default: launch_force_ks<4>(s, grid, block, pos, q, m, vel, wf, rinfo, g.n, g.lines, L, N, kick, nd, F, phi); break;
     }
     return hipGetLastError();
 }

@@ -634,7 +634,8 @@ sce_status run_deposit_split(sce_ctx c, const PassScratch *ps)
     return SCE_OK;
 }
 
-sce_status run_force_split(sce_ctx c, double kick, bool want_phi, const PassScratch *ps)
+sce_status run_force_split(sce_ctx c, double kick, bool want_phi, const PassScratch *ps,
+                           const sce::Drift &nd)
 {
     EventPair ep{nullptr, nullptr};
     if (c->timing && !ps) {
@@ -643,17 +644,23 @@ sce_status run_force_split(sce_ctx c, double kick, bool want_phi, const PassScra
         if (ep.a) HIPCHK(c, hipEventRecord(ep.a, c->stream));
     }
     const bool tent = c->field == SCE_FIELD_TENT;
+    // the next step's half kick and drift ride in the force kernel, but for
+    // the tent field, whose force is completed by the combine below
     HIPCHK(c, sce::launch_force_mfma(c->stream, c->pos, c->q, c->m, c->vel, (const _Float16 *)c->wf,
                                      reinterpret_cast<const float4 *>(c->wscr), c->g, c->L, c->N,
-                                     tent ? 0.0 : kick, tent ? c->Fk : c->F,
+                                     tent ? 0.0 : kick, tent ? sce::Drift{} : nd, tent ? c->Fk : c->F,
                                      tent ? c->Pk : (want_phi ? c->phi : nullptr)));
     if (ep.a && ep.b) {
         HIPCHK(c, hipEventRecord(ep.b, c->stream));
         c->ev_frc.push_back(ep);
     }
-    if (tent)
+    if (tent) {
         HIPCHK(c, sce::launch_tent_combine(c->stream, c->env, c->q, c->m, c->Fk, c->Pk, c->N, kick,
                                            c->vel, c->F, c->phi));
+        if (nd.kick != 0.0 || nd.drift != 0.0)
+            HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L, nd.kick,
+                                             nd.drift, nd.wrap != 0));
+    }
     c->force_valid = true;
     c->phi_valid = want_phi || tent;
     return SCE_OK;
@@ -669,21 +676,36 @@ sce_status deposit(sce_ctx c, const PassScratch *ps = nullptr)
     return fail(c, SCE_ENOTSUP, "precision not available");
 }
 
-sce_status force(sce_ctx c, double kick, bool want_phi, const PassScratch *ps = nullptr)
+// nd: the next leapfrog step's opening half kick and drift, applied after the
+// force and its kick (inside the split-precision force kernel, else by a
+// kick-drift launch); the fields and force are then those of the positions
+// before the drift.
+sce_status force(sce_ctx c, double kick, bool want_phi, const PassScratch *ps = nullptr,
+                 const sce::Drift &nd = sce::Drift{})
 {
-    if (c->prec == SCE_PREC_FP64) return run_force<double>(c, kick, ps);
-    if (c->prec == SCE_PREC_FP32) return run_force<float>(c, kick, ps);
-    if (c->prec == SCE_PREC_SPLIT_F16) return run_force_split(c, kick, want_phi, ps);
-    return fail(c, SCE_ENOTSUP, "precision not available");
+    sce_status st;
+    if (c->prec == SCE_PREC_SPLIT_F16) {
+        st = run_force_split(c, kick, want_phi, ps, nd);
+    } else {
+        if (c->prec == SCE_PREC_FP64) st = run_force<double>(c, kick, ps);
+        else if (c->prec == SCE_PREC_FP32) st = run_force<float>(c, kick, ps);
+        else return fail(c, SCE_ENOTSUP, "precision not available");
+        if (!st && (nd.kick != 0.0 || nd.drift != 0.0))
+            HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L, nd.kick,
+                                             nd.drift, nd.wrap != 0));
+    }
+    if (!st && nd.drift != 0.0) c->fields_valid = c->force_valid = c->phi_valid = false;
+    return st;
 }
 
 // One pass of the hot path at the current positions: deposit, solve, force
-// (+kick); the potential at the particles too when want_phi.
-sce_status pass(sce_ctx c, double kick, bool want_phi = false, const PassScratch *ps = nullptr)
+// (+kick, and nd); the potential at the particles too when want_phi.
+sce_status pass(sce_ctx c, double kick, bool want_phi = false, const PassScratch *ps = nullptr,
+                const sce::Drift &nd = sce::Drift{})
 {
     sce_status st = deposit(c, ps);
     if (st) return st;
-    return force(c, kick, want_phi, ps);
+    return force(c, kick, want_phi, ps, nd);
 }
 
 // Bytes of scratch one pass needs at the context's size and precision, laid
@@ -1058,17 +1080,37 @@ sce_status sce_force_noalloc(sce_ctx c, double *F, int32_t on_device)
 
 namespace {
 
+// k >= 1 kick-drift-kick steps: their launches on the context's stream.  A
+// step's closing half kick and the next step's opening half kick and drift
+// run in one pass after the force (same operations, same order as separate
+// launches, so the states are bit for bit those of k single steps); the
+// velocities are at an integer step only after the last one.
+sce_status steps_kdk(sce_ctx c, double dt, int64_t k)
+{
+    sce_status st;
+    const bool wrap = c->field != SCE_FIELD_TENT;
+    if (!c->force_valid && (st = pass(c, 0.0))) return st;
+    HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L, 0.5 * dt, dt, wrap));
+    c->fields_valid = c->force_valid = c->phi_valid = false;
+    sce::Drift nd;
+    nd.kick = 0.5 * dt;
+    nd.drift = dt;
+    nd.wrap = wrap ? 1 : 0;
+    for (int64_t i = 1; i < k; ++i)
+        if ((st = pass(c, 0.5 * dt, false, nullptr, nd))) return st;
+    if ((st = pass(c, 0.5 * dt))) return st;
+    c->step += k;
+    c->time += k * dt;
+    return SCE_OK;
+}
+
 // One leapfrog step: its launches on the context's stream.
 sce_status step_once(sce_ctx c, double dt)
 {
     sce_status st;
     const bool wrap = c->field != SCE_FIELD_TENT;
     if (c->scheme == SCE_SCHEME_KDK) {
-        if (!c->force_valid && (st = pass(c, 0.0))) return st;
-        HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
-                                         0.5 * dt, dt, wrap));
-        c->fields_valid = c->force_valid = false;
-        if ((st = pass(c, 0.5 * dt))) return st;
+        return steps_kdk(c, dt, 1);
     } else {
         HIPCHK(c, sce::launch_kick_drift(c->stream, c->pos, c->vel, c->F, c->m, c->N, c->L,
                                          0.0, 0.5 * dt, wrap));
@@ -1104,7 +1146,10 @@ sce_status capture_steps(sce_ctx c, double dt)
     const bool fv = c->fields_valid, cv = c->force_valid, pv = c->phi_valid;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
     sce_status st = SCE_OK;
-    for (int i = 0; i < c->graph_steps && !st; ++i) st = step_once(c, dt);
+    if (c->scheme == SCE_SCHEME_KDK)
+        st = steps_kdk(c, dt, c->graph_steps);
+    else
+        for (int i = 0; i < c->graph_steps && !st; ++i) st = step_once(c, dt);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
     c->step = step0;
@@ -1177,6 +1222,7 @@ sce_status sce_step(sce_ctx c, double dt, int64_t n_steps)
             c->time += G * dt;
         }
     }
+    if (s < n_steps && c->scheme == SCE_SCHEME_KDK) return steps_kdk(c, dt, n_steps - s);
     for (; s < n_steps; ++s)
         if ((st = step_once(c, dt))) return st;
     return SCE_OK;

@@ -28,4 +28,13 @@ __device__ inline double frac_lin(int a, double ta, int b, double tb)
 // (cos, sin)(2 pi u)
 __device__ inline void cis_turns(double u, double &c, double &s) { sincospi(2.0 * u, &s, &c); }
 
+// x wrapped into [0, L): x - L floor(x / L), and a result that rounds to L
+// (or a non-finite one) becomes 0.
+__device__ inline double wrap_box(double x, double L, double invL)
+{
+    double w = x - L * floor(x * invL);
+    if (w >= L || w < 0.0) w = 0.0;
+    return w;
+}
+
 }  // namespace sce

@@ -132,9 +132,20 @@ size_t force_pack_bytes(const Geom &g);
 size_t force_rowinfo_bytes(const Geom &g);
 hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0, const Geom &g,
                              float4 *rinfo, _Float16 *wf);
-hipError_t launch_force_mfma(hipStream_t s, const double *pos, const double *q, const double *m,
+// After the force and its kick, optionally the next leapfrog step's first
+// half kick v += kick F / m and drift x += drift v (wrapped into [0, L) when
+// wrap), with the operations of launch_kick_drift: a KDK step's closing half
+// kick, the next step's opening half kick and its drift in one pass (F
+// required).
+struct Drift {
+    double kick = 0.0;
+    double drift = 0.0;
+    int wrap = 0;
+};
+hipError_t launch_force_mfma(hipStream_t s, double *pos, const double *q, const double *m,
                              double *vel, const _Float16 *wf, const float4 *rinfo, const Geom &g,
-                             double L, int64_t N, double kick, double *F, double *phi);
+                             double L, int64_t N, double kick, const Drift &nd, double *F,
+                             double *phi);
 
 // v += a F/m (if a != 0); x = x + b v (if b != 0), wrapped into [0, L) when wrap.
 hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *F,
