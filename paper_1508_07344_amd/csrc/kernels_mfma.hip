@@ -980,8 +980,9 @@ k_force_mfma(double *__restrict__ pos, const double *__restrict__ q,
             for (int s = 0; s < KS; ++s) acc[nt] = mfma_split(ah[s], al[s], bh[nt][s], bl[nt][s], acc[nt]);
             // one tile's products back to back (see mfma_split); with a single
             // K step the chain is short, and interleaving the tiles hides its
-            // latency better
-            if constexpr (KS > 1) __builtin_amdgcn_sched_barrier(0);
+            // latency better.  Not in the variant with the potential, which
+            // then needs more than 128 VGPRs.
+            if constexpr (KS > 1 && !PHI) __builtin_amdgcn_sched_barrier(0);
         }
     };
     auto epilogue = [&](const half8 *wl, int tt, int t, const f32x4 (&acc)[NT]) {
@@ -1076,7 +1077,7 @@ k_force_mfma(double *__restrict__ pos, const double *__restrict__ q,
                 vel[N + j] += a * Fy;
                 vel[2 * N + j] += a * Fz;
             }
-            if (nd.kick != 0.0 || nd.drift != 0.0) {
+            if (!PHI && (nd.kick != 0.0 || nd.drift != 0.0)) {
                 // the next step's first half kick and drift, as a separate
                 // kick-drift pass would apply them (same operations in the
                 // same order); this thread is the only one that reads x_j
@@ -1118,7 +1119,9 @@ hipError_t launch_force_mfma(hipStream_t s, double *pos, const double *q, const 
                              double L, int64_t N, double kick, const Drift &nd, double *F,
                              double *phi)
 {
-    if ((nd.kick != 0.0 || nd.drift != 0.0) && !F) return hipErrorInvalidValue;
+    // the next step's kick and drift: with F, and not in the variant that
+    // also sums the potential
+    if ((nd.kick != 0.0 || nd.drift != 0.0) && (!F || phi)) return hipErrorInvalidValue;
     const int ks = (g.n + 15) / 16;
     const int64_t blocks = (N + kForceBlockParticles - 1) / kForceBlockParticles;
     const dim3 grid((unsigned)blocks), block(64 * kForceWaves);

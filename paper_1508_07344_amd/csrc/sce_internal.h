@@ -136,7 +136,7 @@ hipError_t launch_force_pack(hipStream_t s, const float *ftab, const float *psi0
 // half kick v += kick F / m and drift x += drift v (wrapped into [0, L) when
 // wrap), with the operations of launch_kick_drift: a KDK step's closing half
 // kick, the next step's opening half kick and its drift in one pass (F
-// required).
+// required, phi not: the potential's variant does not take them).
 struct Drift {
     double kick = 0.0;
     double drift = 0.0;
