@@ -492,7 +492,13 @@ k_deposit_mfma(const float *__restrict__ img, int64_t N, int n, int lines, int R
                     form(cur);
                     multiply(c, cur);
                 } else {
+                    // a late wave's products take issue priority over the
+                    // early wave's, so that they end first and its vector
+                    // work for the next chunk overlaps the early wave's
+                    // products instead of trailing them
+                    __builtin_amdgcn_s_setprio(2);
                     multiply(c, cur);
+                    __builtin_amdgcn_s_setprio(0);
                     if (c + 1 < nchunks) form(nxt);
                 }
             }
