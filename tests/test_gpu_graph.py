@@ -80,3 +80,36 @@ def test_step_graph_argument_checks():
         for bad in (-1, 4097):
             with pytest.raises(sce.SceError):
                 c.sce_set_step_graph(bad)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "split_f16"])
+@pytest.mark.parametrize("case", ["plasma3d", "plasma2d", "tent3d"])
+def test_multi_step_call_matches_single_steps(prec, case):
+    """One sce_step call of n kick-drift-kick steps applies a step's closing
+    half kick, the next step's opening half kick and its drift in one pass
+    after the force (inside the split-precision force kernel); the states must
+    be bit for bit those of n calls of one step each, graphs off (direct
+    launches) and on."""
+    sce = _gpu()
+    p = {"plasma3d": workloads.random_plasma(N=20000, n_max=8, a=0.05, sigma_v=0.05),
+         "plasma2d": workloads.random_plasma_2d(N=20000, n_max=12, a=0.03, sigma_v=0.05),
+         "tent3d": workloads.tent_plasma(N=3000, n_max=6)}[case]
+    states = {}
+    for mode in ("single", "direct", "graph"):
+        with sce.Context.from_particles(p, precision=prec, scheme="kdk") as c:
+            c.sce_set_small_step(0)
+            c.sce_set_step_graph(4 if mode == "graph" else 0)
+            if mode == "single":
+                for _ in range(11):
+                    c.sce_step(p.dt, 1)
+            else:
+                c.sce_step(p.dt, 11)
+            x, v = c.sce_get_particles()
+            d, _ = c.sce_diagnostics()
+            states[mode] = (x, v, d.total, d.step)
+    xs, vs, es, ss = states["single"]
+    for mode in ("direct", "graph"):
+        x, v, e, s = states[mode]
+        print(f"{case} {prec} {mode}: max|dx| {np.max(np.abs(x - xs)):.1e}", flush=True)
+        assert s == ss == 11
+        assert np.array_equal(x, xs) and np.array_equal(v, vs) and e == es
