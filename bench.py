@@ -37,6 +37,9 @@ DTYPE = {"fp64": "f64", "fp32": "f32", "split_f16": "f16"}
 # Algorithmic flops per particle x mode pair, counted as complex multiply-adds
 # of the separable sums: deposit 1 complex MAC (8), force 2 complex MACs (16).
 FLOPS_PER_PAIR = {"deposit": 8, "force": 16}
+# Matrix-core flops the split kernels issue per pair (three FP16 products per
+# real product; the deposit's real-form sums serve +-k_y and +-n_z together).
+MFMA_ISSUED_PER_PAIR = {"deposit": 12, "force": 24}
 
 
 def parse():
@@ -180,11 +183,21 @@ def roofline(r, N, peaks=None):
            "frac": round(rates[dom] / peak, 4), "traffic": traffic,
            "other_kernel": {"kernel": kern[other][0], "achieved": round(rates[other], 3),
                             "frac": round(rates[other] / peak, 4)}}
+    if mf:
+        # matrix-core flops the split kernels issue: three products per real
+        # product, and the real-form sums serve the +-k_y and +-n_z modes of
+        # a row pair together (12 per pair in the deposit, 24 in the force)
+        for k, o in ((dom, out), (other, out["other_kernel"])):
+            o["issued"] = round(rates[k] * MFMA_ISSUED_PER_PAIR[k] / FLOPS_PER_PAIR[k], 3)
+            o["issued_frac"] = round(o["issued"] / peak, 4)
     if peaks:
         pm = peaks[PEAK_PROBE[r["precision"]]]
         out["peak_measured"] = pm
         out["frac_measured"] = round(rates[dom] / pm, 4)
         out["other_kernel"]["frac_measured"] = round(rates[other] / pm, 4)
+        if mf:
+            out["issued_frac_measured"] = round(out["issued"] / pm, 4)
+            out["other_kernel"]["issued_frac_measured"] = round(out["other_kernel"]["issued"] / pm, 4)
     return out
 
 
