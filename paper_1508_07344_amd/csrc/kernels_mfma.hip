@@ -744,7 +744,10 @@ __host__ __device__ inline int force_row(int pr, int n, const ForceQuads &f, int
 // One wave per (quad, K step): the 16 lanes of each of the quad's four rows
 // (m / 4 fixed) first find the row's scale together, reading the whole row
 // (all K steps), then each lane packs its 8 entries; the K step 0 wave writes
-// the row records.
+// the row records.  The kernel is small and bound by load latency, so every
+// load a lane makes is issued before the first wait: its 8 entries, psi(r, 0)
+// and (for n_max <= 16) its whole share of the row, from addresses clamped
+// into the row, with the values past the row's n_max entries dropped.
 __global__ void __launch_bounds__(256)
 k_force_pack(const float *__restrict__ ftab, const float *__restrict__ psi0, int n, int lines,
              int nzp, int nzk, int ks, float4 *__restrict__ rinfo, _Float16 *__restrict__ wf)
@@ -762,18 +765,48 @@ k_force_pack(const float *__restrict__ ftab, const float *__restrict__ psi0, int
     const int e = mrow & 3;
     int nx = 0, ny = 0;
     const int r = force_row(pr, n, f, nx, ny);
+    const bool ok = r >= 0;
+    const float *fr = ftab + (int64_t)(ok ? r : 0) * nzp * 8;
+    // entry of the force table packed by component e: cos terms sig_r, sig_i,
+    // nz del_r, nz del_i (0, 1, 4, 5), sin terms -del_i, del_r, -nz sig_i,
+    // nz sig_r (3, 2, 7, 6)
+    //   Re U0 = sig_r cos - del_i sin        Im U0 = sig_i cos + del_r sin
+    //   Re U1 = nz (del_r cos - sig_i sin)   Im U1 = nz (del_i cos + sig_r sin)
+    const int cbase = 4 * (e >> 1);
+    float v[8];
+    bool use[8], neg[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = 32 * s + 8 * (lane >> 4) + i;
+        const bool is_sin = k >= nzk;
+        const int nz = (is_sin ? k - nzk : k) + 1;
+        use[i] = ok && nz <= n;
+        neg[i] = is_sin && !(e & 1);
+        const int comp = cbase + (is_sin ? 3 - (e & 1) : (e & 1));
+        v[i] = fr[(use[i] ? nz - 1 : 0) * 8 + comp];
+    }
+    const float2 p0 = reinterpret_cast<const float2 *>(psi0)[ok ? r : 0];
     // the row's largest |entry|: lane (e, lane group g) reads entries e + 4 g + 16 j
     float mx = 0.f;
-    if (r >= 0) {
-        const float *fr = ftab + (int64_t)r * nzp * 8;
-        for (int i = e + 4 * (lane >> 4); i < n * 8; i += 16) mx = fmaxf(mx, fabsf(fr[i]));
+    const int i0 = e + 4 * (lane >> 4);
+    for (int j0 = 0; j0 < 8 * n; j0 += 16 * 8) {
+        float a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + j0 + 16 * u;
+            const bool in = i < 8 * n;
+            a[u] = fr[in ? i : 0];
+            if (!in) a[u] = 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mx = fmaxf(mx, fabsf(a[u]));
     }
+    if (!ok) mx = 0.f;
     for (int o = 1; o <= 32; o <<= 1)
         if (o != 4 && o != 8) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
     float inv = 1.0f;
-    if (r >= 0) {
-        const float pre = psi0[2 * r], pim = psi0[2 * r + 1];
-        mx = fmaxf(mx, ldexpf(fmaxf(fabsf(pre), fabsf(pim)), -60));
+    if (ok) {
+        mx = fmaxf(mx, ldexpf(fmaxf(fabsf(p0.x), fabsf(p0.y)), -60));
         int ex = 0;
         if (mx > 0.f) {
             frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
@@ -782,7 +815,7 @@ k_force_pack(const float *__restrict__ ftab, const float *__restrict__ psi0, int
         const float sc = mx > 0.f ? ldexpf(1.0f, ex) : 1.0f;
         inv = mx > 0.f ? ldexpf(1.0f, -ex) : 1.0f;
         if (s == 0 && e == 0 && lane < 16) {
-            rinfo[2 * pr] = make_float4(pre * inv, pim * inv, 0.f, 0.f);
+            rinfo[2 * pr] = make_float4(p0.x * inv, p0.y * inv, 0.f, 0.f);
             rinfo[2 * pr + 1] = make_float4((float)nx * sc, (float)ny * sc, sc, 0.f);
         }
     } else if (s == 0 && e == 0 && lane < 16) {
@@ -792,21 +825,8 @@ k_force_pack(const float *__restrict__ ftab, const float *__restrict__ psi0, int
     _Float16 hi[8], lo[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int k = 32 * s + 8 * (lane >> 4) + i;
-        const bool is_sin = k >= nzk;
-        const int nz = (is_sin ? k - nzk : k) + 1;
-        float v = 0.f;
-        if (r >= 0 && nz <= n) {
-            const float *fe = ftab + ((int64_t)r * nzp + (nz - 1)) * 8;
-            // fe: sig_r sig_i del_r del_i nz*del_r nz*del_i nz*sig_r nz*sig_i
-            switch (e) {
-            case 0: v = is_sin ? -fe[3] : fe[0]; break;  // Re U0: sig_r cos - del_i sin
-            case 1: v = is_sin ? fe[2] : fe[1]; break;   // Im U0: sig_i cos + del_r sin
-            case 2: v = is_sin ? -fe[7] : fe[4]; break;  // Re U1: nz (del_r cos - sig_i sin)
-            default: v = is_sin ? fe[6] : fe[5]; break;  // Im U1: nz (del_i cos + sig_r sin)
-            }
-        }
-        split_f16(v * inv, hi[i], lo[i]);
+        const float x = use[i] ? (neg[i] ? -v[i] : v[i]) : 0.f;
+        split_f16(x * inv, hi[i], lo[i]);
     }
     _Float16 *o = wf + ((((int64_t)t * ks + s) * 2) * 64 + lane) * 8;
 #pragma unroll
