@@ -32,6 +32,10 @@ kinetic K = 1/2 sum m |v|^2, field W (see ``field_energy``), total E = K + W,
 interaction sum_j q_j Phi_j (= 2 W), and the constant self-energy of the
 retained modes W_self = (sum q^2 / (eps0 V)) sum_H S^2 / |k|^2.
 
+``cpu_paper`` is not part of the oracle: it is a faster CPU program (the
+paper's per-axis powers, Section 8) that the benchmark times beside it, pinned
+against the oracle by ``tests/test_cpu_paper.py``.
+
 Parity: all functions here are pinned by ``tests/test_oracle_pins.py`` (FFT
 special case, Ewald alpha-independence, rock-salt Madelung constant, gradient,
 adjointness, conservation laws, reversibility, h^2 energy error, cold-plasma
@@ -59,12 +63,15 @@ SHAPES = {"delta": 0, "gaussian": 1, "tent": 2}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE: no fast-math)."""
+    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE: no fast-math),
+    and the CPU comparison baseline of ``cpu_paper`` beside it."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+    from . import cpu_paper
+    cpu_paper.build(force)
     return _LIB
 
 
