@@ -63,7 +63,7 @@ def parse():
                     help="requests sampled for the per-request force error against FP64")
     ap.add_argument("--peaks", type=int, default=1,
                     help="measure the matrix-core and vector throughput peaks (libsce_peak.so)")
-    ap.add_argument("--study", default="", choices=["", "longrun", "dispersion", "h2", "twod", "tent"],
+    ap.add_argument("--study", default="", choices=["", "longrun", "dispersion", "h2", "twod", "tent", "medium"],
                     help="run one validation study instead of the throughput benchmark")
     ap.add_argument("--long-steps", type=int, default=100000,
                     help="steps of the long-run conservation study")
@@ -575,6 +575,44 @@ def study_twod(sce, steps):
     return out
 
 
+def study_medium(sce, steps):
+    """The two n_max = 16 workloads of the longer runs: the 65,536-particle
+    random plasma and the 262,144-particle two-species plasma, KDK, in every
+    precision.  Wall time per step over 10 * steps (split) or 2 * steps
+    (FP32, FP64) steps after 10 warmup steps, without timing events; then the
+    deposit and force times from the library's events over 20 more steps."""
+    import torch
+    import workloads
+    rows = []
+    for name, p in (("random_plasma_65536_n16", workloads.random_plasma()),
+                    ("two_species_262144_n16", workloads.two_species())):
+        for prec in ("split_f16", "fp32", "fp64"):
+            n = 10 * steps if prec == "split_f16" else 2 * steps
+            with sce.Context.from_particles(p, precision=prec, scheme="kdk") as c:
+                c.sce_step(p.dt, 10)
+                c.sce_sync()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c.sce_step(p.dt, n)
+                c.sce_sync()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                c.sce_timing_enable(True)
+                c.sce_step(p.dt, 20)
+                tm = c.sce_timing_read()
+                c.sce_timing_enable(False)
+                H = c.sce_mode_count()
+            ms = 1e3 * (t1 - t0) / n
+            rows.append({"workload": name, "precision": prec, "steps": n, "ms_per_step": round(ms, 5),
+                         "pairs_per_s": p.N * H / (ms * 1e-3),
+                         "deposit_ms_avg": round(tm["deposit_ms"] / max(tm["deposit_launches"], 1), 5),
+                         "force_ms_avg": round(tm["force_ms"] / max(tm["force_launches"], 1), 5)})
+            print(f"medium study {name} {prec}: {ms:.4f} ms/step", file=sys.stderr, flush=True)
+    return {"study": "medium", "rows": rows,
+            "workload": "random_plasma (N = 65,536, n_max = 16, a = 0.02) and two_species "
+                        "(N = 262,144, n_max = 16, m_ion = 100), KDK"}
+
+
 def study_tent(sce, steps, warmup, precisions):
     """Finite-width (tent) field shapes at the size of the headline workload:
     N = 1,048,576 point charges uniform in [-L/4, L/4]^3, n_max = 32 (the
@@ -717,6 +755,8 @@ def main():
             r = study_twod(sce, a.twod_steps)
         elif a.study == "tent":
             r = study_tent(sce, a.steps, a.warmup, [x for x in a.tent_precisions.split(",") if x])
+        elif a.study == "medium":
+            r = study_medium(sce, a.steps)
         else:
             r = study_h2(sce)
         print(json.dumps(r), flush=True)
