@@ -24,7 +24,8 @@
  * pass over the mode table.  The deposit keeps one box of sums per thread and
  * adds them in thread order at the end; the force writes each particle once.
  * Powers are formed by repeated complex multiplication from one sincos per
- * coordinate (about k ulps of rounding at power k).
+ * coordinate (about k ulps of rounding at power k).  Both sums return 0, or
+ * -1 when a work buffer cannot be allocated (the output is then not written).
  */
 #include <math.h>
 #include <stdint.h>
@@ -83,8 +84,8 @@ void sce_cpu_paper_set_threads(int32_t n)
  * S: the shape factor per mode of H (canonical order).  Per thread, the sums
  * of a row (n_x, n_y) are two arrays over n_z (real and imaginary parts), and
  * the row loop runs over n_z for each particle of the block. */
-void sce_cpu_paper_deposit(int64_t N, const double *x, const double *y, const double *z,
-                           const double *q, double L, int32_t n, const double *S, double *rho)
+int32_t sce_cpu_paper_deposit(int64_t N, const double *x, const double *y, const double *z,
+                              const double *q, double L, int32_t n, const double *S, double *rho)
 {
     const int M = 2 * n + 1;
     const size_t box = (size_t)(n + 1) * M * M;
@@ -93,8 +94,9 @@ void sce_cpu_paper_deposit(int64_t N, const double *x, const double *y, const do
     nt = omp_get_max_threads();
 #endif
     double *acc = (double *)calloc((size_t)nt * box * 2, sizeof(double));
-    if (!acc) return;
-#pragma omp parallel
+    if (!acc) return -1;
+    int failed = 0;
+#pragma omp parallel num_threads(nt)
     {
         int t = 0;
 #ifdef _OPENMP
@@ -103,11 +105,16 @@ void sce_cpu_paper_deposit(int64_t N, const double *x, const double *y, const do
         double *are = acc + (size_t)t * box * 2, *aim = are + box;
         /* per particle of the block: x and y powers (k = -n..n), z powers */
         double *tab = (double *)malloc(sizeof(double) * M * PB * 6);
+        if (!tab) {
+#pragma omp atomic write
+            failed = 1;
+        }
         double *xc = tab, *xs = xc + M * PB, *yc = xs + M * PB, *ys = yc + M * PB;
         double *zc = ys + M * PB, *zs = zc + M * PB;
         const int64_t nblk = (N + PB - 1) / PB;
 #pragma omp for schedule(static)
         for (int64_t b = 0; b < nblk; ++b) {
+            if (!tab) continue;
             const int64_t j0 = b * PB;
             const int np = N - j0 < PB ? (int)(N - j0) : PB;
             double qq[PB];
@@ -139,6 +146,10 @@ void sce_cpu_paper_deposit(int64_t N, const double *x, const double *y, const do
         }
         free(tab);
     }
+    if (failed) {
+        free(acc);
+        return -1;
+    }
     /* threads' sums in thread order, read out over H in canonical order */
     int64_t c = 0;
     for (int nx = 0; nx <= n; ++nx)
@@ -156,20 +167,22 @@ void sce_cpu_paper_deposit(int64_t N, const double *x, const double *y, const do
                 ++c;
             }
     free(acc);
+    return 0;
 }
 
 /* F [3][N] = 2 q_j sum_{n in H} k_n Im(psi_n exp(i k_n . x_j)); psi: 2 doubles
  * per mode of H in canonical order.  Per row (n_x, n_y), the block's
  * particles take T = sum_nz psi e_z^nz and Tz = sum_nz n_z psi e_z^nz side by
  * side (the z powers stored particle-fastest), then Im(e_x^nx e_y^ny T). */
-void sce_cpu_paper_force(int64_t N, const double *x, const double *y, const double *z,
-                         const double *q, double L, int32_t n, const double *psi, double *F)
+int32_t sce_cpu_paper_force(int64_t N, const double *x, const double *y, const double *z,
+                            const double *q, double L, int32_t n, const double *psi, double *F)
 {
     const int M = 2 * n + 1;
     const size_t box = (size_t)(n + 1) * M * M;
     /* psi on the dense box (real parts, then imaginary parts), zero outside H */
     double *pre = (double *)calloc(box * 2, sizeof(double));
-    if (!pre) return;
+    if (!pre) return -1;
+    int failed = 0;
     double *pim = pre + box;
     {
         int64_t c = 0;
@@ -186,11 +199,16 @@ void sce_cpu_paper_force(int64_t N, const double *x, const double *y, const doub
 #pragma omp parallel
     {
         double *tab = (double *)malloc(sizeof(double) * M * PB * 6);
+        if (!tab) {
+#pragma omp atomic write
+            failed = 1;
+        }
         double *xc = tab, *xs = xc + M * PB, *yc = xs + M * PB, *ys = yc + M * PB;
         double *zc = ys + M * PB, *zs = zc + M * PB;
         const int64_t nblk = (N + PB - 1) / PB;
 #pragma omp for schedule(static)
         for (int64_t b = 0; b < nblk; ++b) {
+            if (!tab) continue;
             const int64_t j0 = b * PB;
             const int np = N - j0 < PB ? (int)(N - j0) : PB;
             for (int p = 0; p < PB; ++p) {
@@ -241,4 +259,5 @@ void sce_cpu_paper_force(int64_t N, const double *x, const double *y, const doub
         free(tab);
     }
     free(pre);
+    return failed ? -1 : 0;
 }

@@ -44,9 +44,9 @@ def _load():
             P = ctypes.c_void_p
             i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
             lib.sce_cpu_paper_deposit.argtypes = [i64, P, P, P, P, f64, i32, P, P]
-            lib.sce_cpu_paper_deposit.restype = None
+            lib.sce_cpu_paper_deposit.restype = i32
             lib.sce_cpu_paper_force.argtypes = [i64, P, P, P, P, f64, i32, P, P]
-            lib.sce_cpu_paper_force.restype = None
+            lib.sce_cpu_paper_force.restype = i32
             lib.sce_cpu_paper_threads.argtypes = []
             lib.sce_cpu_paper_threads.restype = i32
             lib.sce_cpu_paper_set_threads.argtypes = [i32]
@@ -83,7 +83,8 @@ def deposit(pos, q, L: float, n_max: int, S: np.ndarray) -> np.ndarray:
     q = np.ascontiguousarray(q, dtype=np.float64)
     S = np.ascontiguousarray(S, dtype=np.float64)
     out = np.zeros(2 * len(S))
-    lib.sce_cpu_paper_deposit(len(q), _p(x), _p(y), _p(z), _p(q), float(L), int(n_max), _p(S), _p(out))
+    if lib.sce_cpu_paper_deposit(len(q), _p(x), _p(y), _p(z), _p(q), float(L), int(n_max), _p(S), _p(out)):
+        raise MemoryError("cpu_paper.deposit: work buffers")
     return out[0::2] + 1j * out[1::2]
 
 
@@ -95,5 +96,6 @@ def force(pos, q, L: float, n_max: int, psi_c: np.ndarray) -> np.ndarray:
     ps = np.empty(2 * len(psi_c))
     ps[0::2], ps[1::2] = np.real(psi_c), np.imag(psi_c)
     F = np.zeros(3 * len(q))
-    lib.sce_cpu_paper_force(len(q), _p(x), _p(y), _p(z), _p(q), float(L), int(n_max), _p(ps), _p(F))
+    if lib.sce_cpu_paper_force(len(q), _p(x), _p(y), _p(z), _p(q), float(L), int(n_max), _p(ps), _p(F)):
+        raise MemoryError("cpu_paper.force: work buffers")
     return F.reshape(3, len(q))
