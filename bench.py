@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--precision", default="split_f16", choices=["fp64", "fp32", "split_f16"])
     ap.add_argument("--also", default="fp64,fp32", help="comma list of extra precisions to time")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--n16", type=int, default=1,
+                    help="also time the split step of the two n_max = 16 workloads (informational)")
     ap.add_argument("--cpu-sample", type=int, default=49152,
                     help="particles in the oracle's timed sample (all modes)")
     ap.add_argument("--cpu-paper-sample", type=int, default=262144,
@@ -575,6 +577,28 @@ def study_twod(sce, steps):
     return out
 
 
+def n16_split_steps(sce):
+    """Wall time per split step of the two n_max = 16 workloads (the
+    65,536-particle random plasma, the 262,144-particle two-species plasma),
+    reported beside the headline line for information: 200 and 100 KDK steps
+    after 10 warmup steps, no timing events."""
+    import torch
+    import workloads
+    out = {}
+    for name, p, n in (("random_plasma_65536", workloads.random_plasma(), 200),
+                       ("two_species_262144", workloads.two_species(), 100)):
+        with sce.Context.from_particles(p, precision="split_f16", scheme="kdk") as c:
+            c.sce_step(p.dt, 10)
+            c.sce_sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.sce_step(p.dt, n)
+            c.sce_sync()
+            torch.cuda.synchronize()
+            out[name] = round(1e3 * (time.perf_counter() - t0) / n, 5)
+    return out
+
+
 def study_medium(sce, steps):
     """The two n_max = 16 workloads of the longer runs: the 65,536-particle
     random plasma and the 262,144-particle two-species plasma, KDK, in every
@@ -802,6 +826,8 @@ def main():
     }
     if peaks:
         line["peaks_measured_tflops"] = peaks
+    if a.n16:
+        line["n16_split_ms_per_step"] = n16_split_steps(sce)
     if a.serve_requests:
         line["serving"] = serving(sce, a.serve_requests,
                                   [float(x) for x in a.serve_loads.split(",") if x], a.serve_check)
