@@ -289,10 +289,17 @@ k_serve_reduce(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
 }
 
 // ------------------------------------------------------------------ force + kick + drift
-// Item idx: particles 64 idx .. 64 idx + 63 (one per lane); wave w sums rows
-// [w R / 4, (w+1) R / 4).  The four waves' sums are added in fixed order, then
-// wave 0 applies the pass's kick and drift and writes the item's diagnostics
-// partials (a fixed shuffle tree, so repeated runs give identical bits).
+// Item idx: particles 64 idx .. 64 idx + 63 (one per lane); wave w of the
+// item's kFrcWaves sums rows [w R / kFrcWaves, (w+1) R / kFrcWaves).  The
+// waves' sums are added in fixed order, then wave 0 applies the pass's kick
+// and drift and writes the item's diagnostics partials (a fixed shuffle tree,
+// so repeated runs give identical bits).  Eight waves per item rather than
+// four: a tick's largest requests (n_max = 16, 545 rows) then finish in half
+// the time, and each SIMD holds two of an item's waves (measured saturated
+// capacity +17%; five or ten waves, which spread unevenly over the four
+// SIMDs, were slower than four).  Along an n_x line the row phase follows an
+// FP64 recurrence in n_y from one exponential at the line's start.
+constexpr int kFrcWaves = 8;
 template <typename T, int NZ>
 __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
                          const char *__restrict__ tabs, double *shd)
@@ -332,16 +339,16 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
     const T *__restrict__ ftab = reinterpret_cast<const T *>(tabs + d.o_ftab);
     const T *__restrict__ psi0 = reinterpret_cast<const T *>(tabs + d.o_psi0);
     const int n = d.n, R = d.R;
-    const int r0 = (R * w) / 4, r1 = (R * (w + 1)) / 4;
+    const int r0 = (R * w) / kFrcWaves, r1 = (R * (w + 1)) / kFrcWaves;
     double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
     int nx, ny;
     row_nxny(r0, n, nx, ny);
     double gc = 1.0, gs = 0.0;
-    int since = 8;
+    bool anchor = true;
     for (int r = r0; r < r1; ++r) {
-        if (since == 8) {
+        if (anchor) {
             cis_turns(frac_lin(nx, tx, ny, ty), gc, gs);
-            since = 0;
+            anchor = false;
         }
         const T *ft = ftab + (int64_t)r * NK * 8;
         T u0r = psi0[2 * r], u0i = psi0[2 * r + 1], u1r = (T)0, u1i = (T)0;
@@ -367,16 +374,13 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
         // next row: n_y + 1 within the line, else the next n_x line (re-anchor)
         if (ny < n) {
             ++ny;
-            ++since;
-            if (since < 8) {
-                const double t = gc * eyc - gs * eys;
-                gs = gs * eyc + gc * eys;
-                gc = t;
-            }
+            const double t = gc * eyc - gs * eys;
+            gs = gs * eyc + gc * eys;
+            gc = t;
         } else {
             ++nx;
             ny = -n;
-            since = 8;
+            anchor = true;
         }
     }
 
@@ -391,7 +395,7 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
     }
     __syncthreads();
     if (w != 0) return;
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < kFrcWaves - 1; ++i) {
         const double *o = shd + (i * 64 + lane) * 4;
         fx += o[0];
         fy += o[1];
@@ -451,14 +455,16 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
 
 // tabs: the arena again, read-only here (force tables only; particle state is
 // read and written through arena), so that the wave-uniform table rows can be
-// fetched with scalar loads.
+// fetched with scalar loads.  FP32: six waves per SIMD (80 VGPRs, three items
+// per compute unit) measured 3% more capacity than five, despite a few
+// spilled registers; FP64 keeps the compiler's choice.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kFrcWaves) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1)))
 k_serve_force(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
               const char *__restrict__ tabs, const ServeItem *__restrict__ items,
               const int *__restrict__ counts)
 {
-    __shared__ double shd[3 * 64 * 4];
+    __shared__ double shd[(kFrcWaves - 1) * 64 * 4];
     if ((int)blockIdx.x >= counts[2]) return;
     const ServeItem it = items[blockIdx.x];
     const ReqDesc &d = desc[it.slot];
@@ -525,7 +531,7 @@ hipError_t tick(hipStream_t s, const ReqDesc *desc, char *arena, const ServeItem
     if (gred > 0)
         hipLaunchKernelGGL(k_serve_reduce<T>, dim3(gred), dim3(256), 0, s, desc, arena, red, counts);
     if (gfrc > 0)
-        hipLaunchKernelGGL(k_serve_force<T>, dim3(gfrc), dim3(256), 0, s, desc, arena,
+        hipLaunchKernelGGL(k_serve_force<T>, dim3(gfrc), dim3(64 * kFrcWaves), 0, s, desc, arena,
                            (const char *)arena, frc, counts);
     if (gslots > 0)
         hipLaunchKernelGGL(k_serve_diag, dim3(gslots), dim3(64), 0, s, const_cast<ReqDesc *>(desc),
