@@ -24,7 +24,9 @@ namespace sce {
 // belong on a context of their own.
 constexpr int kServeMaxN = 16;
 // Particles per deposit segment (one partial sum per segment and row tile).
-constexpr int kServeSeg = 512;
+// 256 gave 2-3% more saturated capacity than 512 (shorter items at the end
+// of a tick); 128 and 1,024 gave less.
+constexpr int kServeSeg = 256;
 // Doubles per force work item in the diagnostics partials.
 constexpr int kServeFDiag = 12;
 // Doubles per request of the diagnostics record: first pass [0..7], last pass [8..15]:
