@@ -235,7 +235,29 @@ k_serve_reduce(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
             const int64_t Rp = d.Rp, sstride = (int64_t)nzs * 4 * Rp;
             const T *pp = part + (int64_t)nz * 4 * Rp + row;
             double Pr = 0.0, Pi = 0.0, Qr = 0.0, Qi = 0.0;
-            for (int sg = 0; sg < d.segs; ++sg, pp += sstride) {
+            // four segments' values are loaded before any is added, so that
+            // their loads are in flight together (one segment at a time, the
+            // loop waited for each); the additions keep the segment order
+            int sg = 0;
+            for (; sg + 3 < d.segs; sg += 4, pp += 4 * sstride) {
+                T v[4][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const T *qq = pp + u * sstride;
+                    v[u][0] = qq[0];
+                    v[u][1] = qq[Rp];
+                    v[u][2] = qq[2 * Rp];
+                    v[u][3] = qq[3 * Rp];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    Pr += (double)v[u][0];
+                    Pi += (double)v[u][1];
+                    Qr += (double)v[u][2];
+                    Qi += (double)v[u][3];
+                }
+            }
+            for (; sg < d.segs; ++sg, pp += sstride) {
                 Pr += (double)pp[0];
                 Pi += (double)pp[Rp];
                 Qr += (double)pp[2 * Rp];
