@@ -500,9 +500,9 @@ k_serve_force(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
 }
 
 // ------------------------------------------------------------------ diagnostics + pass count
-// One wave per resident request: lane l sums the item partials l, l+64, ...
-// in order, a fixed shuffle tree adds the lanes; records the first and last
-// pass's diagnostics and counts the pass.
+// One wave per resident request: counts the pass, and on the first and the
+// last pass records its diagnostics (lane l sums the item partials l, l+64,
+// ... in order, a fixed shuffle tree adds the lanes).
 __global__ void __launch_bounds__(64)
 k_serve_diag(ReqDesc *__restrict__ desc, char *__restrict__ arena, const int *__restrict__ slots,
              const int *__restrict__ counts)
@@ -510,6 +510,12 @@ k_serve_diag(ReqDesc *__restrict__ desc, char *__restrict__ arena, const int *__
     if ((int)blockIdx.x >= counts[3]) return;
     const int lane = threadIdx.x;
     ReqDesc &d = desc[slots[blockIdx.x]];
+    const int64_t p = d.pass;
+    // only the first and the last pass are recorded
+    if (p != 0 && p != d.n_steps) {
+        if (lane == 0) d.pass = p + 1;
+        return;
+    }
     const double *fpart = reinterpret_cast<const double *>(arena + d.o_fpart);
     const double *rpart = reinterpret_cast<const double *>(arena + d.o_rpart);
     double s[kServeFDiag];
@@ -528,7 +534,6 @@ k_serve_diag(ReqDesc *__restrict__ desc, char *__restrict__ arena, const int *__
     }
     if (lane != 0) return;
     double *diag = reinterpret_cast<double *>(arena + d.o_diag);
-    const int64_t p = d.pass;
     if (p == 0) {
         const double v[8] = {s[0], W, s[10], s[2], s[3], s[4], s[8], mx};
         for (int c = 0; c < 8; ++c) diag[c] = v[c];
