@@ -319,8 +319,10 @@ k_serve_reduce(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
 // capacity +17%; five or ten waves, which spread unevenly over the four
 // SIMDs, were slower than four).  Along an n_x line the row phase follows an
 // FP64 recurrence in n_y from one exponential at the line's start.
+// REC: a recorded pass (the first or the last), which also sums the potential
+// and writes the diagnostics partials; the other passes skip both.
 constexpr int kFrcWaves = 8;
-template <typename T, int NZ>
+template <typename T, int NZ, bool REC>
 __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
                          const char *__restrict__ tabs, double *shd)
 {
@@ -388,12 +390,11 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
             u1i = fma((T)(k + 1), t1i, u1i);
         }
         const double im0 = gc * (double)u0i + gs * (double)u0r;
-        const double re0 = gc * (double)u0r - gs * (double)u0i;
         const double im1 = gc * (double)u1i + gs * (double)u1r;
         fx = fma((double)nx, im0, fx);
         fy = fma((double)ny, im0, fy);
         fz += im1;
-        ph += re0;
+        if (REC) ph += gc * (double)u0r - gs * (double)u0i;
         // next row: n_y + 1 within the line, else the next n_x line (re-anchor)
         if (ny < n) {
             ++ny;
@@ -442,23 +443,27 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
         const double a = S == 0 ? 0.0 : ((p == 0 || p == S) ? 0.5 * d.dt : d.dt);
         const double b = p < S ? d.dt : 0.0;
         double vx = vel[j], vy = vel[N + j], vz = vel[2 * N + j];
-        double v2 = vx * vx + vy * vy + vz * vz;
-        acc[0] = 0.5 * mj * v2;
-        acc[2] = mj * vx;
-        acc[3] = mj * vy;
-        acc[4] = mj * vz;
-        acc[8] = mj * sqrt(v2);
+        if (REC) {
+            const double v2 = vx * vx + vy * vy + vz * vz;
+            acc[0] = 0.5 * mj * v2;
+            acc[2] = mj * vx;
+            acc[3] = mj * vy;
+            acc[4] = mj * vz;
+            acc[8] = mj * sqrt(v2);
+        }
         const double am = a / mj;
         vx += am * Fx;
         vy += am * Fy;
         vz += am * Fz;
-        v2 = vx * vx + vy * vy + vz * vz;
-        acc[1] = 0.5 * mj * v2;
-        acc[5] = mj * vx;
-        acc[6] = mj * vy;
-        acc[7] = mj * vz;
-        acc[9] = mj * sqrt(v2);
-        acc[10] = qj * 2.0 * ph;
+        if (REC) {
+            const double v2 = vx * vx + vy * vy + vz * vz;
+            acc[1] = 0.5 * mj * v2;
+            acc[5] = mj * vx;
+            acc[6] = mj * vy;
+            acc[7] = mj * vz;
+            acc[9] = mj * sqrt(v2);
+            acc[10] = qj * 2.0 * ph;
+        }
         vel[j] = vx;
         vel[N + j] = vy;
         vel[2 * N + j] = vz;
@@ -468,6 +473,7 @@ __device__ void frc_body(const ReqDesc &d, int idx, char *__restrict__ arena,
             pos[2 * N + j] = wrap_l(pos[2 * N + j] + b * vz, d.L, d.invL);
         }
     }
+    if (!REC) return;
     double *fpart = reinterpret_cast<double *>(arena + d.o_fpart) + (int64_t)idx * kServeFDiag;
     for (int i = 0; i < kServeFDiag; ++i) {
         double v = acc[i];
@@ -491,12 +497,17 @@ k_serve_force(const ReqDesc *__restrict__ desc, char *__restrict__ arena,
     if ((int)blockIdx.x >= counts[2]) return;
     const ServeItem it = items[blockIdx.x];
     const ReqDesc &d = desc[it.slot];
-    if (d.nzs == 5)
-        frc_body<T, 5>(d, it.idx, arena, tabs, shd);
-    else if (d.nzs == 9)
-        frc_body<T, 9>(d, it.idx, arena, tabs, shd);
-    else
-        frc_body<T, 17>(d, it.idx, arena, tabs, shd);
+    const bool rec = d.pass == 0 || d.pass == d.n_steps;
+    if (d.nzs == 5) {
+        if (rec) frc_body<T, 5, true>(d, it.idx, arena, tabs, shd);
+        else frc_body<T, 5, false>(d, it.idx, arena, tabs, shd);
+    } else if (d.nzs == 9) {
+        if (rec) frc_body<T, 9, true>(d, it.idx, arena, tabs, shd);
+        else frc_body<T, 9, false>(d, it.idx, arena, tabs, shd);
+    } else {
+        if (rec) frc_body<T, 17, true>(d, it.idx, arena, tabs, shd);
+        else frc_body<T, 17, false>(d, it.idx, arena, tabs, shd);
+    }
 }
 
 // ------------------------------------------------------------------ diagnostics + pass count
